@@ -1,0 +1,266 @@
+"""Synthetic inputs: geometries, initial colour fields and parameter sets.
+
+This module holds no arithmetic of the lattice Boltzmann method itself: it builds solid masks,
+sharp initial red/blue density fields (node-centre test), analytic wall normals of circular
+obstacles and parabolic inlet profiles.  Both the GPU library's tests and the CPU oracle take
+their inputs from here.
+
+Coordinates are lattice indices (x = column, y = row).  Walls are half-way between a solid
+node and a fluid node, so a solid bottom row y = 0 puts the wall at y = 0.5.  Channel sizes
+quoted as fluid extents (e.g. 2000 x 100) get one extra solid row at the bottom and the top.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+SEED = 170700198
+
+PHYS_KEYS = ("nu_r", "nu_b", "sigma", "beta", "theta_deg", "s_e", "s_eps", "s_q", "rho0",
+             "eps", "outlet_u")
+
+
+@dataclasses.dataclass
+class Setup:
+    """One lattice and its parameters."""
+    name: str
+    solid: np.ndarray            # (ny, nx) uint8, 1 = solid
+    rho_r0: np.ndarray           # (ny, nx) initial red density
+    rho_b0: np.ndarray           # (ny, nx) initial blue density
+    params: dict                 # physical parameters (PHYS_KEYS subset)
+    open_x: bool = False         # velocity inlet at x = 0, convective outlet at x = nx-1
+    inlet_ux: Optional[np.ndarray] = None   # (ny,) inlet velocity profile
+    ns: Optional[np.ndarray] = None         # (ny, nx, 2) analytic wall normal into the solid
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def ny(self):
+        return self.solid.shape[0]
+
+    @property
+    def nx(self):
+        return self.solid.shape[1]
+
+    @property
+    def fluid_nodes(self):
+        return int((self.solid == 0).sum())
+
+    def oracle_kwargs(self):
+        return dict(open_x=self.open_x, ns=self.ns, inlet_ux=self.inlet_ux, **self.params)
+
+
+def _phys(**kw):
+    d = dict(nu_r=1.0 / 6.0, nu_b=1.0 / 6.0, sigma=0.01, beta=0.7, theta_deg=90.0,
+             s_e=1.64, s_eps=1.54, s_q=1.9, rho0=1.0, eps=1e-10, outlet_u=0.0)
+    d.update(kw)
+    return d
+
+
+def _colour_fields(solid, red_mask, rho0=1.0):
+    fluid = solid == 0
+    rr = np.where(fluid & red_mask, rho0, 0.0)
+    rb = np.where(fluid & ~red_mask, rho0, 0.0)
+    return rr, rb
+
+
+def _grid(ny, nx):
+    y, x = np.mgrid[0:ny, 0:nx]
+    return x.astype(np.float64), y.astype(np.float64)
+
+
+def channel_solid(nx, h):
+    """nx columns, h fluid rows between a solid bottom row and a solid top row."""
+    solid = np.zeros((h + 2, nx), dtype=np.uint8)
+    solid[0, :] = 1
+    solid[-1, :] = 1
+    return solid
+
+
+def poiseuille_profile(ny, u_max, y_lo=1, y_hi=None):
+    """Parabolic profile with maximum u_max over fluid rows y_lo..y_hi (walls half-way)."""
+    if y_hi is None:
+        y_hi = ny - 2
+    h = y_hi - y_lo + 1
+    u = np.zeros(ny)
+    for y in range(y_lo, y_hi + 1):
+        yh = y - y_lo + 0.5
+        u[y] = 4.0 * u_max * yh * (h - yh) / (h * h)
+    return u
+
+
+# ---------------------------------------------------------------- paper setups
+
+def droplet_flat(nx=200, h=100, radius=30.0, theta_deg=60.0, nu_r=1.0 / 6.0, nu_b=None,
+                 sigma=0.01, xc=None, yc=None, name="droplet_flat"):
+    """Red droplet on the bottom wall of an x-periodic channel (solid rows at top/bottom).
+    Default: 200 x 100 fluid, radius 30 centred on the wall, theta = 60 deg, nu = 1/6,
+    sigma = 0.01."""
+    solid = channel_solid(nx, h)
+    x, y = _grid(*solid.shape)
+    xc = nx / 2.0 if xc is None else xc
+    yc = 0.5 if yc is None else yc
+    red = (x - xc) ** 2 + (y - yc) ** 2 <= radius ** 2
+    rr, rb = _colour_fields(solid, red)
+    p = _phys(nu_r=nu_r, nu_b=nu_r if nu_b is None else nu_b, sigma=sigma, theta_deg=theta_deg)
+    return Setup(name, solid, rr, rb, p, meta=dict(wall_y=0.5, xc=xc, yc=yc, radius=radius))
+
+
+def droplet_box(theta_deg=60.0, M=1.0, nx=160, ny=100, radius=45.0, nu_r=0.35, sigma=0.02):
+    """Flat-wall droplet of Table I: closed nx x ny box (solid frame), radius 45, centre
+    (nx/2, 3/2 - R cos(theta)) in the paper's 1-based indices, nu_R = 0.35, sigma = 0.02."""
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[0, :] = solid[-1, :] = 1
+    solid[:, 0] = solid[:, -1] = 1
+    x, y = _grid(ny, nx)
+    xc = nx / 2.0 - 1.0
+    yc = 0.5 - radius * math.cos(math.radians(theta_deg))
+    red = (x - xc) ** 2 + (y - yc) ** 2 <= radius ** 2
+    rr, rb = _colour_fields(solid, red)
+    p = _phys(nu_r=nu_r, nu_b=nu_r / M, sigma=sigma, theta_deg=theta_deg)
+    return Setup(f"droplet_box_t{theta_deg:g}_M{M:g}", solid, rr, rb, p,
+                 meta=dict(wall_y=0.5, xc=xc, yc=yc, radius=radius))
+
+
+def free_droplet(n=100, radius=20.0, sigma=0.01, nu=1.0 / 6.0, M=1.0):
+    """Free red droplet in a fully periodic n x n box (no solid)."""
+    solid = np.zeros((n, n), dtype=np.uint8)
+    x, y = _grid(n, n)
+    c = (n - 1) / 2.0
+    red = (x - c) ** 2 + (y - c) ** 2 <= radius ** 2
+    rr, rb = _colour_fields(solid, red)
+    return Setup(f"free_droplet_R{radius:g}", solid, rr, rb,
+                 _phys(nu_r=nu, nu_b=nu / M, sigma=sigma), meta=dict(xc=c, yc=c, radius=radius))
+
+
+def cylinder_droplet(n=200, rc=40.0, rd=40.0, theta_deg=90.0, ccx=100.0, ccy=60.0,
+                     analytic_normals=False, nu=1.0 / 6.0, sigma=0.01, name=None):
+    """Droplet of radius rd resting on a solid cylinder of radius rc in a periodic n x n box.
+    The droplet centre sits at distance D = sqrt(rd^2 + rc^2 - 2 rd rc cos(theta)) above the
+    cylinder centre, so that the two circles meet at the prescribed angle."""
+    x, y = _grid(n, n)
+    solid = (((x - ccx) ** 2 + (y - ccy) ** 2) <= rc ** 2).astype(np.uint8)
+    th = math.radians(theta_deg)
+    D = math.sqrt(rd * rd + rc * rc - 2.0 * rd * rc * math.cos(th))
+    dcx, dcy = ccx, ccy + D
+    red = (x - dcx) ** 2 + (y - dcy) ** 2 <= rd ** 2
+    rr, rb = _colour_fields(solid, red)
+    ns = None
+    if analytic_normals:
+        dx, dy = ccx - x, ccy - y
+        r = np.hypot(dx, dy)
+        r[r == 0] = 1.0
+        ns = np.stack([dx / r, dy / r], axis=-1)
+    return Setup(name or f"cylinder_t{theta_deg:g}", solid, rr, rb,
+                 _phys(nu_r=nu, nu_b=nu, sigma=sigma, theta_deg=theta_deg), ns=ns,
+                 meta=dict(ccx=ccx, ccy=ccy, rc=rc, rd=rd, dcx=dcx, dcy=dcy))
+
+
+def fingering_channel(nx=2000, h=100, x_interface=200.0, M=10.0, theta_deg=60.0, ca=0.1,
+                      nu_r=0.5, sigma=0.01, name=None):
+    """Displacement channel: red (displacing, left) injected with a Poiseuille inlet of mean
+    speed U = Ca sigma / nu_R (maximum 1.5 U), convective outlet with speed U, blue ahead of
+    the interface at x_interface, viscosity ratio M = nu_R / nu_B."""
+    solid = channel_solid(nx, h)
+    x, _ = _grid(*solid.shape)
+    red = x < x_interface
+    rr, rb = _colour_fields(solid, red)
+    U = ca * sigma / nu_r
+    inlet = poiseuille_profile(solid.shape[0], 1.5 * U)
+    p = _phys(nu_r=nu_r, nu_b=nu_r / M, sigma=sigma, theta_deg=theta_deg, outlet_u=U)
+    return Setup(name or f"fingering_{nx}x{h}", solid, rr, rb, p, open_x=True, inlet_ux=inlet,
+                 meta=dict(U=U, u0=1.5 * U, ca=ca, M=M, x_interface=x_interface))
+
+
+def capillary(nx=400, ny=35, plate_x0=100, plate_x1=300, thick=7, blue_x0=120, blue_x1=375,
+              theta_deg=30.0, M=1.0, nu_r=0.5, sigma=0.005):
+    """Capillary filling box of Sec. III C: periodic, plates of thickness `thick` at
+    plate_x0 <= x <= plate_x1 along the bottom and top rows, blue for blue_x0 <= x <= blue_x1."""
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[:thick, plate_x0:plate_x1 + 1] = 1
+    solid[ny - thick:, plate_x0:plate_x1 + 1] = 1
+    x, _ = _grid(ny, nx)
+    blue = (x >= blue_x0) & (x <= blue_x1)
+    rr, rb = _colour_fields(solid, ~blue)
+    return Setup(f"capillary_t{theta_deg:g}_M{M:g}", solid, rr, rb,
+                 _phys(nu_r=nu_r, nu_b=nu_r / M, sigma=sigma, theta_deg=theta_deg),
+                 meta=dict(d=ny - 2 * thick, L=plate_x1 - plate_x0 + 1, inlet_x=plate_x0 - 0.5,
+                           front_x0=blue_x0 - 0.5))
+
+
+def layered_channel(nx=4, h=40, core=20, nu_r=1.0 / 6.0, nu_b=1.0 / 6.0, sigma=0.01):
+    """x-periodic channel with a red core of `core` rows centred between blue layers."""
+    solid = channel_solid(nx, h)
+    _, y = _grid(*solid.shape)
+    mid = (solid.shape[0] - 1) / 2.0
+    red = np.abs(y - mid) < core / 2.0
+    rr, rb = _colour_fields(solid, red)
+    return Setup("layered", solid, rr, rb, _phys(nu_r=nu_r, nu_b=nu_b, sigma=sigma),
+                 meta=dict(mid=mid, core=core, h=h))
+
+
+# ------------------------------------------------------------- workload configs
+
+def cfg_droplet_flat():
+    """Static droplet on a flat wall: 200 x 100 fluid, x periodic, radius 30 on the bottom
+    wall, theta = 60 deg, M = 1, nu = 1/6, sigma = 0.01 (5000 steps)."""
+    return droplet_flat()
+
+
+def cfg_fingering(ca=0.1):
+    """Viscous fingering channel 2000 x 100, M = 10, theta = 60 deg, interface at x = 200."""
+    return fingering_channel(nx=2000, h=100, x_interface=200.0, M=10.0, theta_deg=60.0, ca=ca,
+                             nu_r=0.5, sigma=0.01)
+
+
+def cfg_fingering_large():
+    """Fingering channel 16384 x 512, M = 50, theta = 30 deg, Ca = 0.2, sigma = 0.05,
+    interface at x = 1024."""
+    return fingering_channel(nx=16384, h=512, x_interface=1024.0, M=50.0, theta_deg=30.0,
+                             ca=0.2, nu_r=0.5, sigma=0.05, name="fingering_16384x512")
+
+
+def cfg_sweep(n_channels=320, seed=SEED):
+    """Batched fingering sweep: full factorial M x Ca x theta (160 combos) twice; channel
+    height H drawn by a seeded balanced shuffle (64 channels per H in {50, 75, 100, 150, 200}),
+    length 16 H, interface at 2H + jitter in [-2, 2], nu_R = 0.5, sigma = 0.05."""
+    rng = np.random.default_rng(seed)
+    Ms = [1, 2, 5, 10, 20, 50, 100, 200]
+    Cas = [0.02, 0.05, 0.1, 0.2]
+    thetas = [30, 60, 90, 120, 150]
+    combos = [(M, ca, th) for M in Ms for ca in Cas for th in thetas] * 2
+    combos = combos[:n_channels]
+    Hs = np.array([50, 75, 100, 150, 200] * (len(combos) // 5 + 1))[:len(combos)]
+    rng.shuffle(Hs)
+    jitter = rng.integers(-2, 3, size=len(combos))
+    out = []
+    for k, ((M, ca, th), H, dj) in enumerate(zip(combos, Hs, jitter)):
+        H = int(H)
+        out.append(fingering_channel(nx=16 * H, h=H, x_interface=2.0 * H + int(dj), M=float(M),
+                                     theta_deg=float(th), ca=ca, nu_r=0.5, sigma=0.05,
+                                     name=f"sweep{k:03d}_H{H}_M{M}_Ca{ca}_t{th}"))
+    return out
+
+
+def cfg_wetting_batch(n_cyl=128, n_cap=64, seed=SEED + 1):
+    """Curved-wall droplets (400 x 400 periodic boxes, cylinder radius 40-80, droplet radius
+    20-40, theta 20-160 deg, half analytic / half eighth-order normals) and capillary
+    channels (width 20-60, tube length 1000 in a 2000 x (d + 14) periodic box)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_cyl):
+        rc = float(rng.uniform(40, 80))
+        rd = float(rng.uniform(20, 40))
+        th = float(rng.uniform(20, 160))
+        out.append(cylinder_droplet(n=400, rc=rc, rd=rd, theta_deg=th, ccx=200.0, ccy=160.0,
+                                    analytic_normals=(k % 2 == 0), name=f"cyl{k:03d}"))
+    thetas = [10, 30, 45, 60]
+    Ms = [1, 2, 5, 10]
+    for k in range(n_cap):
+        d = int(rng.integers(20, 61))
+        out.append(capillary(nx=2000, ny=d + 14, plate_x0=500, plate_x1=1499, thick=7,
+                             blue_x0=600, blue_x1=1875, theta_deg=float(thetas[k % 4]),
+                             M=float(Ms[(k // 4) % 4]), nu_r=0.1, sigma=0.05))
+    return out
