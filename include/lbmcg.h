@@ -1,0 +1,135 @@
+/*
+ * lbmcg: MI355X (gfx950) library for the two-colour D2Q9 lattice Boltzmann time step with the
+ * improved geometric wetting boundary of Yu, Liu, Zhang and Liang (arXiv:1707.00198).
+ *
+ * One call of lbm_step advances every domain of a context by the method of Sec. II:
+ * MRT collision with the CSF interfacial force and Guo forcing (Eqs. 1-13, 16-18),
+ * Latva-Kokko/Rothman recolouring (Eq. 14), streaming with half-way bounce-back (Eq. 15),
+ * and the wetting boundary of Sec. II C: virtual colour values on the outermost solid nodes
+ * (Eq. 29), the wall normal from the eighth-order stencil (Eqs. 32-33) or from the caller,
+ * the contact-angle rotation and selection of the colour-gradient direction (Eqs. 30-36),
+ * and virtual interface normals on the outermost solid nodes (Eq. 29 applied to n, which
+ * imposes the zero interface force of Eqs. 19-27 and 37-44).
+ *
+ * Conventions shared by every entry point:
+ *  - A domain is an nx * ny lattice that includes its solid nodes; node (x, y) is element
+ *    y * nx + x of every per-node host array.  Lattice directions follow the paper:
+ *    e0 = (0,0), e1 = (1,0), e2 = (0,1), e3 = (-1,0), e4 = (0,-1), e5 = (1,1), e6 = (-1,1),
+ *    e7 = (-1,-1), e8 = (1,-1).
+ *  - y is periodic; walls are solid nodes of the mask.  x is periodic, or (open_x) has a
+ *    Zou-He velocity inlet at x = 0 and a convective outlet at x = nx - 1.
+ *  - All device pointers belong to the caller and stay owned by the caller; the library
+ *    borrows the state and scratch buffers from lbm_create until lbm_destroy.  The library
+ *    itself owns only the context object and host-side tables.
+ *  - Every call returns an lbm_status; nothing throws across this interface.  The text of
+ *    the last error on the calling thread is returned by lbm_last_error.
+ *  - Work is enqueued on the HIP stream given to lbm_create and is asynchronous unless the
+ *    entry point says otherwise.
+ */
+#ifndef LBMCG_H
+#define LBMCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,      /* invalid argument or parameter (detected before any device work) */
+    LBM_ENOMEM = -2,      /* caller buffer too small */
+    LBM_EDEVICE = -3,     /* a HIP call failed */
+    LBM_ENONFINITE = -4,  /* a non-finite density or velocity appeared on the device */
+    LBM_ESTATE = -5       /* call not valid in the context's current state */
+} lbm_status;
+
+/* Population storage.  Arithmetic is FP64 for LBM_STORE_F64 and FP32 otherwise.  Populations
+ * are stored as deviations f_alpha - w_alpha * rho0; LBM_STORE_F16 stores them in binary16
+ * multiplied by a power-of-two scale per direction.  Colour state is FP64 / FP32. */
+typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_storage;
+
+/* One domain.  Host pointers are read during lbm_create only. */
+typedef struct {
+    int32_t nx, ny;           /* lattice extent including solid nodes; nx >= 2 if open_x */
+    int32_t open_x;           /* 0: periodic x; 1: velocity inlet at x = 0, outlet at nx-1 */
+    int32_t reserved;         /* must be 0 */
+    const uint8_t *solid;     /* nx*ny, nonzero = solid (required) */
+    const double *ns;         /* optional nx*ny*2 wall normal pointing into the solid,
+                                 used on outermost fluid nodes; NULL = eighth-order stencil */
+    const double *inlet_ux;   /* ny inlet velocities (required if open_x, else ignored) */
+    const double *rho_r0;     /* nx*ny initial red density (fluid nodes) */
+    const double *rho_b0;     /* nx*ny initial blue density; rho_r0 + rho_b0 > 0 on fluid */
+    double nu_r, nu_b;        /* kinematic viscosities (> 0), Eqs. 5 and 18 */
+    double sigma;             /* interfacial tension coefficient (>= 0), Eq. 10 */
+    double beta;              /* recolouring segregation parameter in [0, 1], Eq. 14 */
+    double theta_deg;         /* prescribed contact angle in [0, 180], measured in red */
+    double s_e, s_eps, s_q;   /* relaxation rates of e, epsilon, q in (0, 2), Eq. 6 */
+    double rho0;              /* reference density (> 0) of the population deviations */
+    double eps;               /* |grad rho^N| threshold (> 0) below which n = 0 */
+    double outlet_u;          /* convective outlet velocity (>= 0) */
+} lbm_domain_desc;
+
+/* Bytes of device memory the caller must provide for `n` domains stored as `storage`:
+ * `state_bytes` (populations, colour state, open-boundary history; rewritten every step)
+ * and `scratch_bytes` (node classes, wall normals, tables; written once by lbm_create).
+ * Returns LBM_EINVAL for an invalid descriptor. */
+int lbm_query_bytes(const lbm_domain_desc *domains, int n, int storage, size_t *state_bytes,
+                    size_t *scratch_bytes);
+
+/* Validate, classify nodes (fluid, outermost fluid, outermost solid, solid), compute wall
+ * normals, build the tile schedule and upload everything plus the initial state
+ * (f_alpha = rho_k w_alpha, u = 0) into `state_dev` / `scratch_dev` (device pointers of at
+ * least the queried sizes, 256-byte aligned).  `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  Blocks until the upload has finished.  On success *out owns a context. */
+int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_dev,
+               size_t state_bytes, void *scratch_dev, size_t scratch_bytes, void *hip_stream,
+               lbm_ctx **out);
+
+/* Enqueue n_steps time steps of every domain on the context's stream (asynchronous). */
+int lbm_step(lbm_ctx *ctx, int64_t n_steps);
+
+/* Field selection bits for lbm_read_fields. */
+#define LBM_FIELD_RHO_R 1u   /* red density, Eq. 16 (one plane) */
+#define LBM_FIELD_RHO_B 2u   /* blue density (one plane) */
+#define LBM_FIELD_POPS 4u    /* post-streaming populations f_{alpha,k}: 18 planes, colour-major
+                                (red alpha 0..8, then blue alpha 0..8) */
+
+/* Decode domain `domain`'s current state to FP64 into `out_dev` (device pointer, capacity
+ * `out_count` doubles): one nx*ny plane per selected quantity, in bit order; solid nodes
+ * read 0.  Enqueued on the context's stream.  LBM_ENOMEM if out_count is too small. */
+int lbm_read_fields(lbm_ctx *ctx, int domain, uint32_t which, double *out_dev,
+                    size_t out_count);
+
+/* Per-domain FP64 sums over fluid nodes of rho_R and rho_B into out_host[2*d], [2*d + 1].
+ * Synchronises the stream.  Returns LBM_ENONFINITE if a step has produced a non-finite
+ * density or velocity since the context was created. */
+int lbm_mass(lbm_ctx *ctx, double *out_host);
+
+/* Number of time steps taken so far. */
+int64_t lbm_steps_taken(const lbm_ctx *ctx);
+
+/* Tile shape of the fused step: rows per work item (multiple of 4, >= 8).  Rebuilds the
+ * schedule; 0 restores the built-in choice.  Synchronises the stream. */
+int lbm_set_chunk_rows(lbm_ctx *ctx, int rows);
+
+/* Checkpoint: copy the complete mutable state (state buffer contents plus step parity) to
+ * `dst_dev` (device, lbm_state_size bytes) or restore it from `src_dev`.  Stream-ordered. */
+size_t lbm_state_size(const lbm_ctx *ctx);
+int lbm_save_state(lbm_ctx *ctx, void *dst_dev);
+int lbm_load_state(lbm_ctx *ctx, const void *src_dev);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Release the context (does not free the caller's buffers).  Synchronises the stream. */
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMCG_H */

@@ -1,0 +1,530 @@
+// Host runtime of lbmcg: parameter validation, node classification, wall normals, memory
+// layout, tile schedule and the C entry points declared in include/lbmcg.h.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_internal.h"
+#include "lbmcg.h"
+
+using namespace lbmcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+const int EXH[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int EYH[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double WH[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
+size_t colour_bytes(int storage) { return storage == 0 ? 8 : 4; }
+
+// Byte offsets of every region, shared by query and create.
+struct Layout {
+    size_t plane = 0;         // elements per node plane
+    size_t rows = 0;          // total rows (inlet / outlet arrays)
+    size_t items_cap = 0;     // work-item capacity
+    int bpd = 0;              // mass-reduction blocks per domain
+    // state
+    size_t buf[2] = {0, 0}, f_bytes = 0, c_off = 0, vx_off = 0, vy_off = 0, hist[2] = {0, 0};
+    size_t state_bytes = 0;
+    // scratch
+    size_t mask = 0, nsx = 0, nsy = 0, inlet = 0, doms = 0, items = 0, partials = 0,
+           mass_out = 0, flag = 0, scratch_bytes = 0;
+};
+
+int strips_of(const lbm_domain_desc &d) { return (d.nx + TILE_OUT - 1) / TILE_OUT; }
+
+Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
+    Layout L;
+    size_t nodes = 0, rows = 0, cap = 0;
+    for (int i = 0; i < n; i++) {
+        nodes += align_up((size_t)d[i].nx * d[i].ny, 64);
+        rows += d[i].ny;
+        cap += (size_t)strips_of(d[i]) * ((d[i].ny + 7) / 8);
+    }
+    L.plane = align_up(std::max<size_t>(nodes, 64), 128);
+    L.rows = rows;
+    L.items_cap = cap;
+    L.bpd = 16;
+    const size_t sb = storage_bytes(storage), cb = colour_bytes(storage);
+    size_t o = 0;
+    for (int b = 0; b < 2; b++) {
+        L.buf[b] = o;
+        o += align_up(9 * L.plane * sb, 256) + 3 * align_up(L.plane * cb, 256);
+    }
+    L.f_bytes = align_up(9 * L.plane * sb, 256);
+    L.c_off = L.f_bytes;
+    L.vx_off = L.c_off + align_up(L.plane * cb, 256);
+    L.vy_off = L.vx_off + align_up(L.plane * cb, 256);
+    for (int b = 0; b < 2; b++) {
+        L.hist[b] = o;
+        o += align_up(3 * rows * cb, 256);
+    }
+    L.state_bytes = o;
+    o = 0;
+    L.mask = o;
+    o += align_up(L.plane * 2, 256);
+    L.nsx = o;
+    o += align_up(L.plane * cb, 256);
+    L.nsy = o;
+    o += align_up(L.plane * cb, 256);
+    L.inlet = o;
+    o += align_up(rows * cb, 256);
+    L.doms = o;
+    o += align_up(n * sizeof(DomDev), 256);
+    L.items = o;
+    o += align_up(cap * sizeof(WorkItem), 256);
+    L.partials = o;
+    o += align_up((size_t)n * L.bpd * 2 * sizeof(double), 256);
+    L.mass_out = o;
+    o += align_up((size_t)n * 2 * sizeof(double), 256);
+    L.flag = o;
+    o += 256;
+    L.scratch_bytes = o;
+    return L;
+}
+
+int validate(const lbm_domain_desc *d, int n, int storage) {
+    if (!d || n <= 0) return fail(LBM_EINVAL, "need at least one domain");
+    if (storage < 0 || storage > 2) return fail(LBM_EINVAL, "unknown storage %d", storage);
+    for (int i = 0; i < n; i++) {
+        const lbm_domain_desc &q = d[i];
+        if (q.nx < 1 || q.ny < 1) return fail(LBM_EINVAL, "domain %d: bad extent %dx%d", i, q.nx, q.ny);
+        if ((long long)q.nx * q.ny > (1LL << 31)) return fail(LBM_EINVAL, "domain %d too large", i);
+        if (q.open_x && q.nx < 2) return fail(LBM_EINVAL, "domain %d: open x needs nx >= 2", i);
+        if (q.reserved != 0) return fail(LBM_EINVAL, "domain %d: reserved field must be 0", i);
+        if (!q.solid || !q.rho_r0 || !q.rho_b0) return fail(LBM_EINVAL, "domain %d: missing array", i);
+        if (q.open_x && !q.inlet_ux) return fail(LBM_EINVAL, "domain %d: open x needs inlet_ux", i);
+        if (!(q.nu_r > 0) || !(q.nu_b > 0)) return fail(LBM_EINVAL, "domain %d: viscosity must be > 0 (tau > 1/2)", i);
+        if (!(q.sigma >= 0)) return fail(LBM_EINVAL, "domain %d: sigma must be >= 0", i);
+        if (!(q.beta >= 0 && q.beta <= 1)) return fail(LBM_EINVAL, "domain %d: beta outside [0, 1]", i);
+        if (!(q.theta_deg >= 0 && q.theta_deg <= 180)) return fail(LBM_EINVAL, "domain %d: theta outside [0, 180]", i);
+        for (double s : {q.s_e, q.s_eps, q.s_q})
+            if (!(s > 0 && s < 2)) return fail(LBM_EINVAL, "domain %d: relaxation rate outside (0, 2)", i);
+        if (!(q.rho0 > 0) || !(q.eps > 0) || !(q.outlet_u >= 0))
+            return fail(LBM_EINVAL, "domain %d: rho0, eps must be > 0 and outlet_u >= 0", i);
+        const size_t nn = (size_t)q.nx * q.ny;
+        for (size_t k = 0; k < nn; k++) {
+            if (q.solid[k]) continue;
+            const double rr = q.rho_r0[k], rb = q.rho_b0[k];
+            if (!(std::isfinite(rr) && std::isfinite(rb) && rr >= 0 && rb >= 0 && rr + rb > 0))
+                return fail(LBM_EINVAL, "domain %d: invalid initial density at node %zu", i, k);
+        }
+        if (q.open_x)
+            for (int y = 0; y < q.ny; y++)
+                if (!(std::isfinite(q.inlet_ux[y]) && std::fabs(q.inlet_ux[y]) < 0.5))
+                    return fail(LBM_EINVAL, "domain %d: inlet velocity must be finite and |u| < 0.5", i);
+    }
+    return LBM_OK;
+}
+
+// Eighth-order isotropic estimate of the wall normal (Eqs. 32-33), pointing into the solid.
+// Beyond an open x edge the stencil sees fluid.
+void e8_normal(const lbm_domain_desc &q, int x, int y, double &nx, double &ny) {
+    double sx = 0.0, sy = 0.0;
+    for (int cy = -2; cy <= 2; cy++)
+        for (int cx = -2; cx <= 2; cx++) {
+            const int r2 = cx * cx + cy * cy;
+            double w;
+            switch (r2) {
+                case 1: w = 4.0 / 21.0; break;
+                case 2: w = 4.0 / 45.0; break;
+                case 4: w = 1.0 / 60.0; break;
+                case 5: w = 2.0 / 315.0; break;
+                case 8: w = 1.0 / 5040.0; break;
+                default: continue;
+            }
+            int xx = x + cx;
+            const int yy = ((y + cy) % q.ny + q.ny) % q.ny;
+            if (q.open_x && (xx < 0 || xx >= q.nx)) continue;
+            xx = ((xx % q.nx) + q.nx) % q.nx;
+            if (!q.solid[(size_t)yy * q.nx + xx]) continue;
+            sx += w * cx;
+            sy += w * cy;
+        }
+    const double m = std::sqrt(sx * sx + sy * sy);
+    nx = m > 0 ? sx / m : 0.0;
+    ny = m > 0 ? sy / m : 0.0;
+}
+
+template <class T>
+T encode(double v, float scale);
+template <>
+double encode<double>(double v, float) { return v; }
+template <>
+float encode<float>(double v, float) { return (float)v; }
+template <>
+__half encode<__half>(double v, float scale) { return __float2half_rn((float)(v * scale)); }
+
+}  // namespace
+
+struct lbm_ctx {
+    int n = 0, storage = 0;
+    hipStream_t stream = nullptr;
+    char *state = nullptr, *scratch = nullptr;
+    Layout L;
+    std::vector<lbm_domain_desc> desc;   // host pointers are not kept valid: sizes only
+    std::vector<DomDev> doms;
+    std::vector<WorkItem> items;
+    int chunk_rows = 0;
+    int parity = 0;   // buffer holding the current state
+    int own = 1;      // current state is a node-local snapshot
+    int64_t steps = 0;
+    double *mass_host = nullptr;
+    int *flag_host = nullptr;
+};
+
+namespace {
+
+template <class T, class AT>
+void fill_args(const lbm_ctx *c, int parity, StepArgs<T, AT> &A) {
+    const Layout &L = c->L;
+    A.doms = reinterpret_cast<const DomDev *>(c->scratch + L.doms);
+    A.items = reinterpret_cast<const WorkItem *>(c->scratch + L.items);
+    A.n_items = (int)c->items.size();
+    A.own = c->own;
+    char *bi = c->state + L.buf[parity], *bo = c->state + L.buf[1 - parity];
+    A.fin = reinterpret_cast<const T *>(bi);
+    A.cin = reinterpret_cast<const AT *>(bi + L.c_off);
+    A.vxin = reinterpret_cast<const AT *>(bi + L.vx_off);
+    A.vyin = reinterpret_cast<const AT *>(bi + L.vy_off);
+    A.fout = reinterpret_cast<T *>(bo);
+    A.cout = reinterpret_cast<AT *>(bo + L.c_off);
+    A.vxout = reinterpret_cast<AT *>(bo + L.vx_off);
+    A.vyout = reinterpret_cast<AT *>(bo + L.vy_off);
+    A.hist_in = reinterpret_cast<const AT *>(c->state + L.hist[parity]);
+    A.hist_out = reinterpret_cast<AT *>(c->state + L.hist[1 - parity]);
+    A.mask = reinterpret_cast<const uint16_t *>(c->scratch + L.mask);
+    A.nsx = reinterpret_cast<const AT *>(c->scratch + L.nsx);
+    A.nsy = reinterpret_cast<const AT *>(c->scratch + L.nsy);
+    A.inlet = reinterpret_cast<const AT *>(c->scratch + L.inlet);
+    A.plane = L.plane;
+    A.flag = reinterpret_cast<int *>(c->scratch + L.flag);
+}
+
+// Arguments for the current parity, as raw bytes of the storage's StepArgs instantiation.
+struct AnyArgs {
+    alignas(16) unsigned char bytes[sizeof(StepArgs<double, double>)];
+};
+
+AnyArgs make_args(const lbm_ctx *c, int parity) {
+    AnyArgs a;
+    std::memset(&a, 0, sizeof a);
+    if (c->storage == 0) fill_args(c, parity, *reinterpret_cast<StepArgs<double, double> *>(a.bytes));
+    else if (c->storage == 1) fill_args(c, parity, *reinterpret_cast<StepArgs<float, float> *>(a.bytes));
+    else fill_args(c, parity, *reinterpret_cast<StepArgs<__half, float> *>(a.bytes));
+    return a;
+}
+
+std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk) {
+    std::vector<WorkItem> out;
+    for (int i = 0; i < (int)d.size(); i++) {
+        const int ny = d[i].ny;
+        const int nch = std::max(1, (ny + chunk - 1) / chunk);
+        const int ch = ((ny + nch - 1) / nch + 3) / 4 * 4;
+        for (int s = 0; s < strips_of(d[i]); s++)
+            for (int k = 0; k < nch; k++) {
+                const int y0 = k * ch, y1 = std::min(ny, y0 + ch);
+                if (y0 >= y1) continue;
+                out.push_back(WorkItem{i, s * TILE_OUT, y0, y1});
+            }
+    }
+    return out;
+}
+
+int auto_chunk(const std::vector<lbm_domain_desc> &d) {
+    const int cands[] = {128, 96, 64, 48, 32, 24, 16, 12, 8};
+    for (int ch : cands)
+        if (build_items(d, ch).size() >= 2048) return ch;
+    return 8;
+}
+
+int upload_items(lbm_ctx *c) {
+    if (c->items.size() > c->L.items_cap) return fail(LBM_EINVAL, "work-item table overflow");
+    HIP_OK(hipMemcpyAsync(c->scratch + c->L.items, c->items.data(),
+                          c->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+template <class T, class AT>
+int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
+    const Layout &L = c->L;
+    const size_t P = L.plane;
+    std::vector<uint16_t> mask(P, (uint16_t)SELF_SOLID);
+    std::vector<AT> nsx(P, AT(0)), nsy(P, AT(0)), inlet(std::max<size_t>(L.rows, 1), AT(0));
+    std::vector<T> f(9 * P, encode<T>(0.0, 1.0f));
+    std::vector<AT> col(3 * P, AT(0));  // c, vx, vy
+    std::vector<AT> hist(3 * std::max<size_t>(L.rows, 1), AT(0));
+    long long off = 0, io = 0;
+    for (int i = 0; i < c->n; i++) {
+        const lbm_domain_desc &q = d[i];
+        DomDev &D = c->doms[i];
+        const double th = q.theta_deg * M_PI / 180.0;
+        D.off = off;
+        D.nx = q.nx;
+        D.ny = q.ny;
+        D.open_x = q.open_x ? 1 : 0;
+        D.io_off = io;
+        D.inv2nu_r = 1.0 / (2.0 * q.nu_r);
+        D.inv2nu_b = 1.0 / (2.0 * q.nu_b);
+        D.half_sigma = 0.5 * q.sigma;
+        D.beta = q.beta;
+        D.cos_t = std::cos(th);
+        D.sin_t = std::sin(th);
+        D.s_e = q.s_e;
+        D.s_eps = q.s_eps;
+        D.s_q = q.s_q;
+        D.rho0 = q.rho0;
+        D.eps = q.eps;
+        D.outlet_u = q.outlet_u;
+        for (int a = 0; a < 9; a++) {
+            float s = 1.0f;
+            if (c->storage == 2) s = std::ldexp(1.0f, (int)std::lround(std::log2(256.0 / WH[a])));
+            D.scale[a] = s;
+            D.inv_scale[a] = 1.0f / s;
+        }
+        auto solid_at = [&](int x, int y) -> bool {
+            y = ((y % q.ny) + q.ny) % q.ny;
+            if (q.open_x) x = std::min(std::max(x, 0), q.nx - 1);
+            else x = ((x % q.nx) + q.nx) % q.nx;
+            return q.solid[(size_t)y * q.nx + x] != 0;
+        };
+        for (int y = 0; y < q.ny; y++)
+            for (int x = 0; x < q.nx; x++) {
+                const size_t k = (size_t)y * q.nx + x, g = off + k;
+                const bool s = q.solid[k] != 0;
+                uint32_t m = s ? SELF_SOLID : 0u;
+                bool other = false;
+                for (int a = 1; a < 9; a++) {
+                    const bool sn = solid_at(x + EXH[a], y + EYH[a]);
+                    if (sn) m |= 1u << (a - 1);
+                    if (sn != s) other = true;
+                }
+                if (other) m |= s ? SOLID_BND : FLUID_BND;
+                mask[g] = (uint16_t)m;
+                if (!s && other) {
+                    double vx, vy;
+                    if (q.ns) {
+                        vx = q.ns[2 * k];
+                        vy = q.ns[2 * k + 1];
+                        const double mg = std::sqrt(vx * vx + vy * vy);
+                        vx = mg > 0 ? vx / mg : 0.0;
+                        vy = mg > 0 ? vy / mg : 0.0;
+                    } else {
+                        e8_normal(q, x, y, vx, vy);
+                    }
+                    nsx[g] = (AT)vx;
+                    nsy[g] = (AT)vy;
+                }
+                if (s) continue;
+                const double rr = q.rho_r0[k], rb = q.rho_b0[k], rho = rr + rb;
+                for (int a = 0; a < 9; a++) f[a * P + g] = encode<T>(WH[a] * (rho - q.rho0), D.scale[a]);
+                col[g] = (AT)(rr / rho);
+                if (q.open_x && x == q.nx - 1) {
+                    hist[3 * (io + y) + 0] = (AT)(WH[3] * (rho - q.rho0));
+                    hist[3 * (io + y) + 1] = (AT)(WH[6] * (rho - q.rho0));
+                    hist[3 * (io + y) + 2] = (AT)(WH[7] * (rho - q.rho0));
+                }
+            }
+        if (q.open_x)
+            for (int y = 0; y < q.ny; y++) inlet[io + y] = (AT)q.inlet_ux[y];
+        off += (long long)align_up((size_t)q.nx * q.ny, 64);
+        io += q.ny;
+    }
+    hipStream_t s = c->stream;
+    char *st = c->state + L.buf[0];
+    HIP_OK(hipMemsetAsync(c->state, 0, L.state_bytes, s));
+    HIP_OK(hipMemcpyAsync(st, f.data(), 9 * P * sizeof(T), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(st + L.c_off, col.data(), P * sizeof(AT), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(c->state + L.hist[0], hist.data(), 3 * L.rows * sizeof(AT),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemsetAsync(c->scratch, 0, L.scratch_bytes, s));
+    HIP_OK(hipMemcpyAsync(c->scratch + L.mask, mask.data(), P * 2, hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(c->scratch + L.nsx, nsx.data(), P * sizeof(AT), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(c->scratch + L.nsy, nsy.data(), P * sizeof(AT), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(c->scratch + L.inlet, inlet.data(), L.rows * sizeof(AT),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(c->scratch + L.doms, c->doms.data(), c->n * sizeof(DomDev),
+                          hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return upload_items(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_query_bytes(const lbm_domain_desc *domains, int n, int storage, size_t *state_bytes,
+                    size_t *scratch_bytes) {
+    int rc = validate(domains, n, storage);
+    if (rc) return rc;
+    Layout L = make_layout(domains, n, storage);
+    if (state_bytes) *state_bytes = L.state_bytes;
+    if (scratch_bytes) *scratch_bytes = L.scratch_bytes;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_dev,
+               size_t state_bytes, void *scratch_dev, size_t scratch_bytes, void *hip_stream,
+               lbm_ctx **out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(domains, n, storage);
+    if (rc) return rc;
+    Layout L = make_layout(domains, n, storage);
+    if (!state_dev || !scratch_dev) return fail(LBM_EINVAL, "device buffers are NULL");
+    if (state_bytes < L.state_bytes || scratch_bytes < L.scratch_bytes)
+        return fail(LBM_ENOMEM, "buffers too small: need %zu state and %zu scratch bytes",
+                    L.state_bytes, L.scratch_bytes);
+    if (((uintptr_t)state_dev | (uintptr_t)scratch_dev) & 255)
+        return fail(LBM_EINVAL, "device buffers must be 256-byte aligned");
+    lbm_ctx *c = new lbm_ctx();
+    c->n = n;
+    c->storage = storage;
+    c->stream = (hipStream_t)hip_stream;
+    c->state = (char *)state_dev;
+    c->scratch = (char *)scratch_dev;
+    c->L = L;
+    c->desc.assign(domains, domains + n);
+    c->doms.resize(n);
+    c->chunk_rows = auto_chunk(c->desc);
+    c->items = build_items(c->desc, c->chunk_rows);
+    if (hipHostMalloc((void **)&c->mass_host, (2 * (size_t)n + 2) * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void **)&c->flag_host, 64) != hipSuccess) {
+        delete c;
+        return fail(LBM_EDEVICE, "pinned host allocation failed");
+    }
+    if (storage == 0) rc = create_t<double, double>(c, domains);
+    else if (storage == 1) rc = create_t<float, float>(c, domains);
+    else rc = create_t<__half, float>(c, domains);
+    if (rc) {
+        lbm_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n_steps) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (n_steps < 0) return fail(LBM_EINVAL, "negative step count");
+    for (int64_t k = 0; k < n_steps; k++) {
+        AnyArgs a = make_args(c, c->parity);
+        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), 0, c->stream));
+        c->parity ^= 1;
+        c->own = 0;
+        c->steps++;
+    }
+    return LBM_OK;
+}
+
+int lbm_read_fields(lbm_ctx *c, int domain, uint32_t which, double *out_dev, size_t out_count) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (domain < 0 || domain >= c->n) return fail(LBM_EINVAL, "domain %d out of range", domain);
+    if (which == 0 || (which & ~7u)) return fail(LBM_EINVAL, "bad field selection %u", which);
+    if (!out_dev) return fail(LBM_EINVAL, "output is NULL");
+    const lbm_domain_desc &q = c->desc[domain];
+    const size_t planes = ((which & 1u) ? 1 : 0) + ((which & 2u) ? 1 : 0) + ((which & 4u) ? 18 : 0);
+    if (out_count < planes * (size_t)q.nx * q.ny)
+        return fail(LBM_ENOMEM, "output holds %zu doubles, need %zu", out_count, planes * (size_t)q.nx * q.ny);
+    AnyArgs a = make_args(c, c->parity);
+    HIP_OK(launch_read(c->storage, a.bytes, domain, q.nx, q.ny, which, out_dev, c->stream));
+    return LBM_OK;
+}
+
+int lbm_mass(lbm_ctx *c, double *out_host) {
+    if (!c || !out_host) return fail(LBM_EINVAL, "null argument");
+    AnyArgs a = make_args(c, c->parity);
+    double *partials = reinterpret_cast<double *>(c->scratch + c->L.partials);
+    double *mout = reinterpret_cast<double *>(c->scratch + c->L.mass_out);
+    HIP_OK(launch_mass(c->storage, a.bytes, c->n, nullptr, partials, c->L.bpd, mout, c->stream));
+    HIP_OK(hipMemcpyAsync(c->mass_host, mout, 2 * (size_t)c->n * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipMemcpyAsync(c->flag_host, c->scratch + c->L.flag, sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    std::memcpy(out_host, c->mass_host, 2 * (size_t)c->n * sizeof(double));
+    if (*c->flag_host) return fail(LBM_ENONFINITE, "a non-finite density or velocity appeared");
+    return LBM_OK;
+}
+
+int64_t lbm_steps_taken(const lbm_ctx *c) { return c ? c->steps : -1; }
+
+int lbm_set_chunk_rows(lbm_ctx *c, int rows) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (rows != 0 && (rows < 8 || rows % 4)) return fail(LBM_EINVAL, "chunk rows must be 0 or a multiple of 4 >= 8");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->chunk_rows = rows ? rows : auto_chunk(c->desc);
+    c->items = build_items(c->desc, c->chunk_rows);
+    return upload_items(c);
+}
+
+size_t lbm_state_size(const lbm_ctx *c) { return c ? c->L.state_bytes + 256 : 0; }
+
+int lbm_save_state(lbm_ctx *c, void *dst_dev) {
+    if (!c || !dst_dev) return fail(LBM_EINVAL, "null argument");
+    HIP_OK(hipMemcpyAsync(dst_dev, c->state, c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    long long hdr[4] = {0x6c626d6367LL, c->parity, c->own, c->steps};
+    HIP_OK(hipMemcpyAsync((char *)dst_dev + c->L.state_bytes, hdr, sizeof hdr,
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx *c, const void *src_dev) {
+    if (!c || !src_dev) return fail(LBM_EINVAL, "null argument");
+    long long hdr[4];
+    HIP_OK(hipMemcpyAsync(hdr, (const char *)src_dev + c->L.state_bytes, sizeof hdr,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (hdr[0] != 0x6c626d6367LL || (hdr[1] & ~1LL) || (hdr[2] & ~1LL) || hdr[3] < 0)
+        return fail(LBM_ESTATE, "not a saved state of this library");
+    HIP_OK(hipMemcpyAsync(c->state, src_dev, c->L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->parity = (int)hdr[1];
+    c->own = (int)hdr[2];
+    c->steps = hdr[3];
+    return LBM_OK;
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->mass_host) (void)hipHostFree(c->mass_host);
+    if (c->flag_host) (void)hipHostFree(c->flag_host);
+    delete c;
+}
+
+}  // extern "C"

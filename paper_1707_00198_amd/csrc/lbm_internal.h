@@ -1,0 +1,68 @@
+// Internal layout shared by the kernels and the host runtime of lbmcg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbmcg {
+
+// Per-node class word.  Bits 0..7: the stencil neighbour in direction a = 1..8 is solid
+// (bit a-1).  Neighbours wrap periodically in y, and in x unless the x axis is open, where
+// they are clamped to the edge column.
+constexpr uint32_t SELF_SOLID = 1u << 8;
+constexpr uint32_t FLUID_BND = 1u << 9;   // fluid node with a solid neighbour
+constexpr uint32_t SOLID_BND = 1u << 10;  // solid node with a fluid neighbour
+
+constexpr int TILE_LANES = 64;     // columns loaded per tile row (one wavefront)
+constexpr int HALO = 4;            // dependency radius of one step next to walls
+constexpr int TILE_OUT = TILE_LANES - 2 * HALO;  // output columns per tile
+constexpr int TILE_WAVES = 4;      // rows advanced per iteration (one per wavefront)
+constexpr int RING = 8;            // LDS ring depth in rows
+
+struct DomDev {
+    long long off;       // first node of the domain in every node plane
+    int nx, ny;
+    int open_x, pad0;
+    long long io_off;    // first row of the domain in the inlet / outlet row arrays
+    double inv2nu_r, inv2nu_b;
+    double half_sigma, beta, cos_t, sin_t;
+    double s_e, s_eps, s_q, rho0, eps, outlet_u;
+    float scale[9], inv_scale[9];
+};
+
+struct WorkItem {
+    int dom, x0, y0, y1;
+};
+
+// Pointers of one step.  f* are 9 planes of `plane` elements (direction-major), c / vx / vy
+// one plane each (colour state of the node's last collision), hist is the outlet history:
+// [row][3] deviations of f_3, f_6, f_7 at the outlet column.
+template <class T, class AT>
+struct StepArgs {
+    const DomDev *doms;
+    const WorkItem *items;
+    int n_items;
+    int own;  // state is a node-local snapshot: f at its node, c = red fraction, v unused
+    const T *fin;
+    const AT *cin, *vxin, *vyin;
+    T *fout;
+    AT *cout, *vxout, *vyout;
+    const AT *hist_in;
+    AT *hist_out;
+    const uint16_t *mask;
+    const AT *nsx, *nsy;
+    const AT *inlet;
+    size_t plane;
+    int *flag;
+};
+
+// Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16.
+hipError_t launch_step(int storage, const void *args, int n_items, int waves_per_eu_hint,
+                       hipStream_t s);
+hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, uint32_t which,
+                       double *out, hipStream_t s);
+hipError_t launch_mass(int storage, const void *args, int n_doms, const int *dom_nodes_begin,
+                       double *partials, int n_blocks_per_dom, double *out, hipStream_t s);
+
+}  // namespace lbmcg

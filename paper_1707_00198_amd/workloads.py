@@ -136,7 +136,8 @@ def free_droplet(n=100, radius=20.0, sigma=0.01, nu=1.0 / 6.0, M=1.0):
 
 
 def cylinder_droplet(n=200, rc=40.0, rd=40.0, theta_deg=90.0, ccx=100.0, ccy=60.0,
-                     analytic_normals=False, nu=1.0 / 6.0, sigma=0.01, name=None):
+                     analytic_normals=False, nu=1.0 / 6.0, sigma=0.01, name=None,
+                     dcx_offset=0.0):
     """Droplet of radius rd resting on a solid cylinder of radius rc in a periodic n x n box.
     The droplet centre sits at distance D = sqrt(rd^2 + rc^2 - 2 rd rc cos(theta)) above the
     cylinder centre, so that the two circles meet at the prescribed angle."""
@@ -144,7 +145,7 @@ def cylinder_droplet(n=200, rc=40.0, rd=40.0, theta_deg=90.0, ccx=100.0, ccy=60.
     solid = (((x - ccx) ** 2 + (y - ccy) ** 2) <= rc ** 2).astype(np.uint8)
     th = math.radians(theta_deg)
     D = math.sqrt(rd * rd + rc * rc - 2.0 * rd * rc * math.cos(th))
-    dcx, dcy = ccx, ccy + D
+    dcx, dcy = ccx + dcx_offset, ccy + D
     red = (x - dcx) ** 2 + (y - dcy) ** 2 <= rd ** 2
     rr, rb = _colour_fields(solid, red)
     ns = None

@@ -1,0 +1,101 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every entry point
+include/lbmcg.h declares, sizes buffers and rejects invalid parameters before device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1707_00198_amd import lbm, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbmcg.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("lbm_create", "lbm_step", "lbm_read_fields", "lbm_mass", "lbm_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.load_library()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+    assert set(declared_functions()) == set(lbm.PROTOTYPES)
+
+
+def _desc(s):
+    keep = []
+    d = lbm.DomainDesc()
+    solid = np.ascontiguousarray(s.solid, np.uint8)
+    rr = np.ascontiguousarray(s.rho_r0)
+    rb = np.ascontiguousarray(s.rho_b0)
+    keep += [solid, rr, rb]
+    d.nx, d.ny, d.open_x = s.nx, s.ny, int(s.open_x)
+    d.solid = solid.ctypes.data_as(C.POINTER(C.c_uint8))
+    d.rho_r0 = rr.ctypes.data_as(C.POINTER(C.c_double))
+    d.rho_b0 = rb.ctypes.data_as(C.POINTER(C.c_double))
+    if s.open_x:
+        iu = np.ascontiguousarray(s.inlet_ux)
+        keep.append(iu)
+        d.inlet_ux = iu.ctypes.data_as(C.POINTER(C.c_double))
+    for k, v in s.params.items():
+        setattr(d, k, float(v))
+    return d, keep
+
+
+def query(s, storage=0):
+    L = lbm.load_library()
+    d, keep = _desc(s)
+    st, sc = C.c_size_t(), C.c_size_t()
+    rc = L.lbm_query_bytes(C.byref(d), 1, storage, C.byref(st), C.byref(sc))
+    return rc, st.value, sc.value, L.lbm_last_error().decode()
+
+
+def test_query_sizes_scale_with_storage():
+    s = W.cfg_droplet_flat()
+    sizes = [query(s, k)[1] for k in range(3)]
+    assert sizes[0] > sizes[1] > sizes[2]
+    nodes = s.nx * s.ny
+    # two buffers of 9 populations + 3 colour values (+ alignment)
+    assert 2 * nodes * 12 * 8 <= sizes[0] < 2 * nodes * 12 * 8 * 1.2
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(nu_r=0.0), "viscosity"), (dict(nu_b=-1.0), "viscosity"), (dict(theta_deg=181.0), "theta"),
+    (dict(beta=1.5), "beta"), (dict(s_q=2.0), "relaxation"), (dict(eps=0.0), "eps"),
+])
+def test_invalid_parameters_are_rejected(change, msg):
+    s = W.cfg_droplet_flat()
+    s.params = dict(s.params, **change)
+    rc, *_, err = query(s)
+    assert rc == -1 and msg in err
+
+
+def test_invalid_geometry_is_rejected():
+    s = W.cfg_droplet_flat()
+    s.rho_r0 = s.rho_r0.copy()
+    s.rho_r0[5, 5] = np.nan
+    rc, *_, err = query(s)
+    assert rc == -1 and "density" in err
+    s = W.fingering_channel(nx=40, h=8)
+    s.inlet_ux = s.inlet_ux * 1000  # peak 3.0, beyond the lattice speed limit
+    rc, *_, err = query(s)
+    assert rc == -1 and "inlet" in err
+    assert query(s, storage=7)[0] == -1
+
+
+def test_lattice_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        lbm.Lattice([W.cfg_droplet_flat()])
