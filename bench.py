@@ -63,7 +63,7 @@ def time_lattice(setups, storage, steps, warmup, chunk_rows=0):
     from paper_1707_00198_amd.lbm import Lattice
     lat = Lattice(setups, storage=storage)
     if chunk_rows:
-        lat.set_chunk_rows(chunk_rows)
+        lat.set_tile(chunk_rows)
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()

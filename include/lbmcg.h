@@ -89,6 +89,13 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
                size_t state_bytes, void *scratch_dev, size_t scratch_bytes, void *hip_stream,
                lbm_ctx **out);
 
+/* Host-only: node classes and wall normals the library derives for one domain, without any
+ * device work.  classes_out (nx*ny, may be NULL): 0 fluid, 1 outermost fluid (a fluid node with
+ * a solid D2Q9 neighbour), 2 outermost solid (a solid node with a fluid neighbour), 3 other
+ * solid.  ns_out (nx*ny*2, may be NULL): the wall normal used on outermost fluid nodes
+ * (Eqs. 32-33 or the caller's analytic normal, unit length, into the solid), 0 elsewhere. */
+int lbm_classify(const lbm_domain_desc *domain, uint8_t *classes_out, double *ns_out);
+
 /* Enqueue n_steps time steps of every domain on the context's stream (asynchronous). */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 
@@ -112,9 +119,11 @@ int lbm_mass(lbm_ctx *ctx, double *out_host);
 /* Number of time steps taken so far. */
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 
-/* Tile shape of the fused step: rows per work item (multiple of 4, >= 8).  Rebuilds the
- * schedule; 0 restores the built-in choice.  Synchronises the stream. */
-int lbm_set_chunk_rows(lbm_ctx *ctx, int rows);
+/* Tile shape of the fused step: `chunk_rows` rows of a 54-column strip per work item
+ * (multiple of 4, >= 8; 0 = built-in choice) and `waves` tile rows advanced per iteration
+ * (4 or 8; 0 = built-in).  Rebuilds the schedule; results do not depend on the tile shape.
+ * Synchronises the stream. */
+int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves);
 
 /* Checkpoint: copy the complete mutable state (state buffer contents plus step parity) to
  * `dst_dev` (device, lbm_state_size bytes) or restore it from `src_dev`.  Stream-ordered. */

@@ -176,6 +176,40 @@ void e8_normal(const lbm_domain_desc &q, int x, int y, double &nx, double &ny) {
     ny = m > 0 ? sy / m : 0.0;
 }
 
+// Class word of node (x, y) (see lbm_internal.h) and, on outermost fluid nodes, the wall
+// normal: the caller's analytic one (normalised) or the eighth-order estimate.
+uint32_t node_class(const lbm_domain_desc &q, int x, int y, double &nsx, double &nsy) {
+    auto solid_at = [&](int xx, int yy) -> bool {
+        yy = ((yy % q.ny) + q.ny) % q.ny;
+        if (q.open_x) xx = std::min(std::max(xx, 0), q.nx - 1);
+        else xx = ((xx % q.nx) + q.nx) % q.nx;
+        return q.solid[(size_t)yy * q.nx + xx] != 0;
+    };
+    const size_t k = (size_t)y * q.nx + x;
+    const bool s = q.solid[k] != 0;
+    uint32_t m = s ? SELF_SOLID : 0u;
+    bool other = false;
+    for (int a = 1; a < 9; a++) {
+        const bool sn = solid_at(x + EXH[a], y + EYH[a]);
+        if (sn) m |= 1u << (a - 1);
+        if (sn != s) other = true;
+    }
+    if (other) m |= s ? SOLID_BND : FLUID_BND;
+    nsx = nsy = 0.0;
+    if (!s && other) {
+        if (q.ns) {
+            nsx = q.ns[2 * k];
+            nsy = q.ns[2 * k + 1];
+            const double mg = std::sqrt(nsx * nsx + nsy * nsy);
+            nsx = mg > 0 ? nsx / mg : 0.0;
+            nsy = mg > 0 ? nsy / mg : 0.0;
+        } else {
+            e8_normal(q, x, y, nsx, nsy);
+        }
+    }
+    return m;
+}
+
 template <class T>
 T encode(double v, float scale);
 template <>
@@ -196,6 +230,7 @@ struct lbm_ctx {
     std::vector<DomDev> doms;
     std::vector<WorkItem> items;
     int chunk_rows = 0;
+    int waves = 8;    // wavefronts (tile rows advanced per iteration) of the step kernel
     int parity = 0;   // buffer holding the current state
     int own = 1;      // current state is a node-local snapshot
     int64_t steps = 0;
@@ -261,10 +296,12 @@ std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chu
     return out;
 }
 
+// Tallest chunk that still yields enough work items to fill the chip (8 XCDs x 32 CUs, a few
+// resident blocks each); taller chunks repeat fewer halo rows.
 int auto_chunk(const std::vector<lbm_domain_desc> &d) {
     const int cands[] = {128, 96, 64, 48, 32, 24, 16, 12, 8};
     for (int ch : cands)
-        if (build_items(d, ch).size() >= 2048) return ch;
+        if (build_items(d, ch).size() >= 1024) return ch;
     return 8;
 }
 
@@ -313,39 +350,15 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
             D.scale[a] = s;
             D.inv_scale[a] = 1.0f / s;
         }
-        auto solid_at = [&](int x, int y) -> bool {
-            y = ((y % q.ny) + q.ny) % q.ny;
-            if (q.open_x) x = std::min(std::max(x, 0), q.nx - 1);
-            else x = ((x % q.nx) + q.nx) % q.nx;
-            return q.solid[(size_t)y * q.nx + x] != 0;
-        };
         for (int y = 0; y < q.ny; y++)
             for (int x = 0; x < q.nx; x++) {
                 const size_t k = (size_t)y * q.nx + x, g = off + k;
-                const bool s = q.solid[k] != 0;
-                uint32_t m = s ? SELF_SOLID : 0u;
-                bool other = false;
-                for (int a = 1; a < 9; a++) {
-                    const bool sn = solid_at(x + EXH[a], y + EYH[a]);
-                    if (sn) m |= 1u << (a - 1);
-                    if (sn != s) other = true;
-                }
-                if (other) m |= s ? SOLID_BND : FLUID_BND;
+                double vx, vy;
+                const uint32_t m = node_class(q, x, y, vx, vy);
+                const bool s = (m & SELF_SOLID) != 0;
                 mask[g] = (uint16_t)m;
-                if (!s && other) {
-                    double vx, vy;
-                    if (q.ns) {
-                        vx = q.ns[2 * k];
-                        vy = q.ns[2 * k + 1];
-                        const double mg = std::sqrt(vx * vx + vy * vy);
-                        vx = mg > 0 ? vx / mg : 0.0;
-                        vy = mg > 0 ? vy / mg : 0.0;
-                    } else {
-                        e8_normal(q, x, y, vx, vy);
-                    }
-                    nsx[g] = (AT)vx;
-                    nsy[g] = (AT)vy;
-                }
+                nsx[g] = (AT)vx;
+                nsy[g] = (AT)vy;
                 if (s) continue;
                 const double rr = q.rho_r0[k], rb = q.rho_b0[k], rho = rr + rb;
                 for (int a = 0; a < 9; a++) f[a * P + g] = encode<T>(WH[a] * (rho - q.rho0), D.scale[a]);
@@ -402,6 +415,9 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     int rc = validate(domains, n, storage);
     if (rc) return rc;
     Layout L = make_layout(domains, n, storage);
+    if (L.plane * std::max(storage_bytes(storage), colour_bytes(storage)) >= (size_t(1) << 31))
+        return fail(LBM_EINVAL, "%zu nodes exceed one context's limit of 2^31 bytes per node plane",
+                    L.plane);
     if (!state_dev || !scratch_dev) return fail(LBM_EINVAL, "device buffers are NULL");
     if (state_bytes < L.state_bytes || scratch_bytes < L.scratch_bytes)
         return fail(LBM_ENOMEM, "buffers too small: need %zu state and %zu scratch bytes",
@@ -435,12 +451,31 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     return LBM_OK;
 }
 
+int lbm_classify(const lbm_domain_desc *domain, uint8_t *classes_out, double *ns_out) {
+    int rc = validate(domain, 1, 0);
+    if (rc) return rc;
+    const lbm_domain_desc &q = *domain;
+    for (int y = 0; y < q.ny; y++)
+        for (int x = 0; x < q.nx; x++) {
+            double vx, vy;
+            const uint32_t m = node_class(q, x, y, vx, vy);
+            const size_t k = (size_t)y * q.nx + x;
+            if (classes_out)
+                classes_out[k] = (m & SELF_SOLID) ? ((m & SOLID_BND) ? 2 : 3) : ((m & FLUID_BND) ? 1 : 0);
+            if (ns_out) {
+                ns_out[2 * k] = vx;
+                ns_out[2 * k + 1] = vy;
+            }
+        }
+    return LBM_OK;
+}
+
 int lbm_step(lbm_ctx *c, int64_t n_steps) {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (n_steps < 0) return fail(LBM_EINVAL, "negative step count");
     for (int64_t k = 0; k < n_steps; k++) {
         AnyArgs a = make_args(c, c->parity);
-        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), 0, c->stream));
+        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->stream));
         c->parity ^= 1;
         c->own = 0;
         c->steps++;
@@ -480,11 +515,14 @@ int lbm_mass(lbm_ctx *c, double *out_host) {
 
 int64_t lbm_steps_taken(const lbm_ctx *c) { return c ? c->steps : -1; }
 
-int lbm_set_chunk_rows(lbm_ctx *c, int rows) {
+int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves) {
     if (!c) return fail(LBM_EINVAL, "null context");
-    if (rows != 0 && (rows < 8 || rows % 4)) return fail(LBM_EINVAL, "chunk rows must be 0 or a multiple of 4 >= 8");
+    if (chunk_rows != 0 && (chunk_rows < 8 || chunk_rows % 4))
+        return fail(LBM_EINVAL, "chunk rows must be 0 or a multiple of 4 >= 8");
+    if (waves != 0 && waves != 4 && waves != 8) return fail(LBM_EINVAL, "waves must be 0, 4 or 8");
     HIP_OK(hipStreamSynchronize(c->stream));
-    c->chunk_rows = rows ? rows : auto_chunk(c->desc);
+    c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc);
+    c->waves = waves ? waves : 8;
     c->items = build_items(c->desc, c->chunk_rows);
     return upload_items(c);
 }

@@ -14,11 +14,10 @@ constexpr uint32_t SELF_SOLID = 1u << 8;
 constexpr uint32_t FLUID_BND = 1u << 9;   // fluid node with a solid neighbour
 constexpr uint32_t SOLID_BND = 1u << 10;  // solid node with a fluid neighbour
 
-constexpr int TILE_LANES = 64;     // columns loaded per tile row (one wavefront)
-constexpr int HALO = 4;            // dependency radius of one step next to walls
+constexpr int TILE_LANES = 64;     // columns per tile row (one wavefront)
+constexpr int HALO = 5;            // halo columns per side: the step's dependency radius next to
+                                   // walls is 4, plus one column for the colour-state stencil
 constexpr int TILE_OUT = TILE_LANES - 2 * HALO;  // output columns per tile
-constexpr int TILE_WAVES = 4;      // rows advanced per iteration (one per wavefront)
-constexpr int RING = 8;            // LDS ring depth in rows
 
 struct DomDev {
     long long off;       // first node of the domain in every node plane
@@ -58,8 +57,7 @@ struct StepArgs {
 };
 
 // Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16.
-hipError_t launch_step(int storage, const void *args, int n_items, int waves_per_eu_hint,
-                       hipStream_t s);
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, hipStream_t s);
 hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, uint32_t which,
                        double *out, hipStream_t s);
 hipError_t launch_mass(int storage, const void *args, int n_doms, const int *dom_nodes_begin,

@@ -41,6 +41,42 @@ __device__ __forceinline__ AT wgt(int a) {
     return a == 0 ? AT(4.0 / 9.0) : (a < 5 ? AT(1.0 / 9.0) : AT(1.0 / 36.0));
 }
 
+// Reciprocal and square root: IEEE in FP64 (the FP64 path is checked element by element
+// against a plain FP64 evaluation); the hardware's 1-ulp instructions in FP32.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Colour indicator (Eq. 12), exactly +-1 in pure phases.
+__device__ __forceinline__ double colour_indicator(double rR, double rB) { return (rR - rB) / (rR + rB); }
+__device__ __forceinline__ float colour_indicator(float rR, float rB) {
+    return rB == 0.0f ? 1.0f : (rR == 0.0f ? -1.0f : (rR - rB) * rcp(rR + rB));
+}
+
+// Unit interface normal (Eq. 22) from a gradient of modulus g > 0.
+__device__ __forceinline__ void unit_normal(double gx, double gy, double g, double &nx, double &ny) {
+    nx = gx / g;
+    ny = gy / g;
+}
+__device__ __forceinline__ void unit_normal(float gx, float gy, float g, float &nx, float &ny) {
+    const float ig = rcp(g);
+    nx = gx * ig;
+    ny = gy * ig;
+}
+
+// Accumulate s +/- w*v.  In FP64 the product is rounded before the sum (no contraction), as in
+// a plain IEEE evaluation: the colour gradient feeds branches (|grad| > eps, the contact-angle
+// selection) whose symmetric ties must round the same way.
+__device__ __forceinline__ double acc_nc(double s, double w, double v, int sign) {
+#pragma clang fp contract(off)
+    const double t = w * v;
+    return sign > 0 ? s + t : s - t;
+}
+__device__ __forceinline__ float acc_nc(float s, float w, float v, int sign) {
+    return sign > 0 ? s + w * v : s - w * v;
+}
+
 // ------------------------------------------------------------------ storage codec
 template <class T>
 struct Codec;
@@ -48,12 +84,16 @@ template <>
 struct Codec<double> {
     using AT = double;
     __device__ static double load(const double *p, float) { return *p; }
+    __device__ static double decode(double v, float) { return v; }
+    __device__ static double encode(double v, float) { return v; }
     __device__ static void store(double *p, double v, float) { *p = v; }
 };
 template <>
 struct Codec<float> {
     using AT = float;
     __device__ static float load(const float *p, float) { return *p; }
+    __device__ static float decode(float v, float) { return v; }
+    __device__ static float encode(float v, float) { return v; }
     __device__ static void store(float *p, float v, float) { *p = v; }
 };
 template <>
@@ -62,117 +102,177 @@ struct Codec<__half> {
     __device__ static float load(const __half *p, float inv_scale) {
         return __half2float(*p) * inv_scale;
     }
+    __device__ static float decode(__half v, float inv_scale) { return __half2float(v) * inv_scale; }
+    __device__ static __half encode(float v, float scale) { return __float2half_rn(v * scale); }
     __device__ static void store(__half *p, float v, float scale) {
         *p = __float2half_rn(v * scale);
     }
 };
 
+// Periodic wrap of an index that is usually already in [0, n): one compare on the fast path.
+// Element access into one node plane with a 32-bit index (uniform base pointer).
+template <class V>
+struct Plane {
+    V *p;
+    __device__ __forceinline__ Plane(const V *b, uint32_t) : p(const_cast<V *>(b)) {}
+    __device__ __forceinline__ V load(uint32_t i) const { return p[i]; }
+    __device__ __forceinline__ void store(uint32_t i, V v) const { p[i] = v; }
+};
+
 __device__ __forceinline__ int wrap(int v, int n) {
+    if ((unsigned)v < (unsigned)n) return v;
     v %= n;
     return v < 0 ? v + n : v;
 }
 
-__device__ __forceinline__ size_t node_at(const DomDev &D, int x, int y) {
-    return (size_t)D.off + (size_t)y * D.nx + x;
-}
+// Neighbourhood of node (x, y) of a domain: node offsets of the rows y-1, y, y+1 (periodic) and
+// the columns x-1, x, x+1 (periodic, or clamped at an open x axis, where lo / hi flag that the
+// column lies beyond the inlet / outlet).
+struct Nbr {
+    size_t row[3];
+    int col[3];
+    bool lo, hi;
+};
 
-// Deviation of the post-streaming total population of direction a at node (x, y), for the
-// interior pull: from the source node, or by half-way bounce-back from the node itself.
-template <class T, class AT>
-__device__ __forceinline__ AT pull_total(const StepArgs<T, AT> &A, const DomDev &D, int x, int y,
-                                         uint32_t m, int a) {
-    if (m & (1u << (OPP[a] - 1))) {
-        return Codec<T>::load(A.fin + OPP[a] * A.plane + node_at(D, x, y), D.inv_scale[OPP[a]]);
-    }
-    int xs = x - EX[a], ys = wrap(y - EY[a], D.ny);
-    if (!D.open_x) xs = wrap(xs, D.nx);
-    return Codec<T>::load(A.fin + a * A.plane + node_at(D, xs, ys), D.inv_scale[a]);
-}
-
-// Post-streaming populations of fluid node (x, y) as deviations d[a], with the colour state
-// (cs, vs) of the collision each one comes from.  Completes inlet (Zou-He, red) and outlet
-// (convective) unknowns; with write_hist the completed outlet values are kept for the next
-// step.
-template <class T, class AT>
-__device__ __forceinline__ void gather(const StepArgs<T, AT> &A, const DomDev &D, int x, int y,
-                                       uint32_t m, bool write_hist, AT d[9], AT cs[9], AT vsx[9],
-                                       AT vsy[9]) {
-    const size_t self = node_at(D, x, y);
-    if (A.own) {
-        const AT c = A.cin[self];
-#pragma unroll
-        for (int a = 0; a < 9; a++) {
-            d[a] = Codec<T>::load(A.fin + a * A.plane + self, D.inv_scale[a]);
-            cs[a] = c;
-            vsx[a] = AT(0);
-            vsy[a] = AT(0);
-        }
+__device__ __forceinline__ Nbr make_nbr(const DomDev &D, int x, int y) {
+    Nbr n;
+    const int ym = y == 0 ? D.ny - 1 : y - 1;
+    const int yp = y == D.ny - 1 ? 0 : y + 1;
+    n.row[0] = (size_t)D.off + (size_t)ym * D.nx;
+    n.row[1] = (size_t)D.off + (size_t)y * D.nx;
+    n.row[2] = (size_t)D.off + (size_t)yp * D.nx;
+    n.col[1] = x;
+    if (D.open_x) {
+        n.lo = x == 0;
+        n.hi = x == D.nx - 1;
+        n.col[0] = n.lo ? x : x - 1;
+        n.col[2] = n.hi ? x : x + 1;
     } else {
-        const AT cself = A.cin[self], vxs = A.vxin[self], vys = A.vyin[self];
+        n.lo = n.hi = false;
+        n.col[0] = x == 0 ? D.nx - 1 : x - 1;
+        n.col[2] = x == D.nx - 1 ? 0 : x + 1;
+    }
+    return n;
+}
+
+// Node the pull of direction a reads from: x - e_a.
+__device__ __forceinline__ size_t pull_src(const Nbr &n, int a) {
+    return n.row[1 - EY[a]] + n.col[1 - EX[a]];
+}
+
+// The pull of direction a crosses the inlet (x = 0, e_x = +1) or the outlet (x = nx-1, e_x = -1).
+__device__ __forceinline__ bool pull_outside(const Nbr &n, int a) {
+    return (n.lo && EX[a] == 1) || (n.hi && EX[a] == -1);
+}
+
+// Completes the post-streaming populations d[] of fluid node (x, y) whose interior pulls are
+// already in d[] (and whose own-node snapshot values are in d[] in snapshot mode): half-way
+// bounce-back on links from solid nodes, Zou-He inlet and convective outlet unknowns; and
+// returns the red and blue densities of Eq. 16.  colour(a, c, vx, vy) yields the colour state
+// of the pull source of direction a (a = 0: the node itself).
+template <class T, class AT, class ColourFn>
+__device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, const DomDev &D, int x, int y,
+                                              uint32_t m, const Nbr &nb, bool write_hist, AT d[9],
+                                              AT &rR, AT &rB, ColourFn colour) {
+    const size_t self = nb.row[1] + x;
+    const AT rho0 = AT(D.rho0);
+    AT cself, vxs, vys;
+    colour(0, cself, vxs, vys);
+    rR = AT(0);
+    rB = AT(0);
+    if (A.own) {
+        // node-local snapshot: every population carries the node's own red fraction
+        AT tot = AT(0);
 #pragma unroll
-        for (int a = 0; a < 9; a++) {
-            if (a == 0) {
-                d[0] = Codec<T>::load(A.fin + self, D.inv_scale[0]);
-                cs[0] = cself;
-                vsx[0] = AT(0);
-                vsy[0] = AT(0);
-                continue;
-            }
-            int xs = x - EX[a];
-            const bool outside = D.open_x && (xs < 0 || xs >= D.nx);
-            if (outside) {  // completed below
-                d[a] = AT(0);
+        for (int a = 0; a < 9; a++) tot += wgt<AT>(a) * rho0 + d[a];
+        rR = cself * tot;
+        rB = tot - rR;
+    } else {
+        AT cs[9], vsx[9], vsy[9];
+        cs[0] = cself;
+        vsx[0] = vsy[0] = AT(0);
+#pragma unroll
+        for (int a = 1; a < 9; a++) {
+            if (pull_outside(nb, a)) {  // completed below
                 cs[a] = cself;
-                vsx[a] = AT(0);
-                vsy[a] = AT(0);
+                vsx[a] = vsy[a] = AT(0);
             } else if (m & (1u << (OPP[a] - 1))) {  // half-way bounce-back
                 d[a] = Codec<T>::load(A.fin + OPP[a] * A.plane + self, D.inv_scale[OPP[a]]);
                 cs[a] = cself;
                 vsx[a] = -vxs;
                 vsy[a] = -vys;
             } else {
-                if (!D.open_x) xs = wrap(xs, D.nx);
-                const size_t s = node_at(D, xs, wrap(y - EY[a], D.ny));
-                d[a] = Codec<T>::load(A.fin + a * A.plane + s, D.inv_scale[a]);
-                cs[a] = A.cin[s];
-                vsx[a] = A.vxin[s];
-                vsy[a] = A.vyin[s];
+                colour(a, cs[a], vsx[a], vsy[a]);
             }
         }
-        if (D.open_x && x == 0) {
+        if (nb.lo) {
             // Zou-He velocity inlet on the total f; injected fluid is pure red.
             const AT u = A.inlet[D.io_off + y];
-            const AT rho = (AT(D.rho0) + d[0] + d[2] + d[4] + AT(2) * (d[3] + d[6] + d[7])) /
-                           (AT(1) - u);
+            const AT rho = (rho0 + d[0] + d[2] + d[4] + AT(2) * (d[3] + d[6] + d[7])) / (AT(1) - u);
             const AT ru = rho * u;
             d[1] = d[3] + AT(2.0 / 3.0) * ru;
             d[5] = d[7] - AT(0.5) * (d[2] - d[4]) + AT(1.0 / 6.0) * ru;
             d[8] = d[6] + AT(0.5) * (d[2] - d[4]) + AT(1.0 / 6.0) * ru;
             cs[1] = cs[5] = cs[8] = AT(1);
         }
-        if (D.open_x && x == D.nx - 1) {
-            // Convective outlet f_a <- [f_a(t) + U f_a(x - 1, t + 1)] / (1 + U), coloured
-            // with this node's red fraction.
+        if (nb.hi) {
+            // Convective outlet f_a <- [f_a(t) + U f_a(x - 1, t + 1)] / (1 + U), coloured with
+            // this node's red fraction.
             const AT U = AT(D.outlet_u);
-            const size_t im = self - 1;
-            const uint32_t mm = A.mask[im];
+            const uint32_t mm = A.mask[self - 1];
             const AT *h = A.hist_in + (D.io_off + y) * 3;
             const int unk[3] = {3, 6, 7};
 #pragma unroll
             for (int q = 0; q < 3; q++) {
                 const int a = unk[q];
                 AT v = h[q];
-                if (!(mm & SELF_SOLID)) v = (v + U * pull_total(A, D, x - 1, y, mm, a)) / (AT(1) + U);
+                if (!(mm & SELF_SOLID)) {
+                    // post-streaming f_a of the neighbour (x - 1, y): from (x, y - e_y) or bounced
+                    const AT inner =
+                        (mm & (1u << (OPP[a] - 1)))
+                            ? Codec<T>::load(A.fin + OPP[a] * A.plane + self - 1, D.inv_scale[OPP[a]])
+                            : Codec<T>::load(A.fin + a * A.plane + nb.row[1 - EY[a]] + x, D.inv_scale[a]);
+                    v = (v + U * inner) / (AT(1) + U);
+                }
                 d[a] = v;
             }
         }
+        // rho_B as the total minus rho_R: exactly 0 where every source is pure red (c = 1,
+        // v = 0), and rho_R exactly 0 where every source is pure blue
+        AT tot = AT(0);
+#pragma unroll
+        for (int a = 0; a < 9; a++) {
+            const AT fa = wgt<AT>(a) * rho0 + d[a];
+            rR += cs[a] * fa + wgt<AT>(a) * (AT(EX[a]) * vsx[a] + AT(EY[a]) * vsy[a]);
+            tot += fa;
+        }
+        rB = tot - rR;
     }
-    if (write_hist && D.open_x && x == D.nx - 1) {
+    if (write_hist && nb.hi) {
         AT *h = A.hist_out + (D.io_off + y) * 3;
         h[0] = d[3];
         h[1] = d[6];
         h[2] = d[7];
     }
+}
+
+// Gather with colour state from global memory (read-back and reductions).
+template <class T, class AT>
+__device__ __forceinline__ void gather_global(const StepArgs<T, AT> &A, const DomDev &D, int x, int y,
+                                              uint32_t m, AT d[9], AT &rR, AT &rB) {
+    const Nbr nb = make_nbr(D, x, y);
+    const size_t self = nb.row[1] + x;
+#pragma unroll
+    for (int a = 0; a < 9; a++) {
+        const size_t src = A.own ? self : pull_src(nb, a);
+        d[a] = Codec<T>::load(A.fin + a * A.plane + src, D.inv_scale[a]);
+    }
+    finish_gather(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
+        const size_t src = (a == 0 || A.own) ? self : pull_src(nb, a);
+        c = A.cin[src];
+        vx = A.own ? AT(0) : A.vxin[src];
+        vy = A.own ? AT(0) : A.vyin[src];
+    });
 }
 
 // Contact-angle correction of the colour gradient on an outermost fluid node (Eqs. 30-36):
@@ -199,38 +299,95 @@ __device__ __forceinline__ void wetting_correct(AT nsx, AT nsy, AT ct, AT st, AT
     }
 }
 
-// Red and blue densities (Eq. 16) of the gathered populations.
+// MRT collision with Guo forcing (Eqs. 1, 2, 8 in moment space) of the deviations d (f = w rho0
+// + d), force F, local colour indicator rN; returns the post-collision deviations in o.
 template <class AT>
-__device__ __forceinline__ void colour_densities(const AT d[9], const AT cs[9], const AT vsx[9],
-                                                 const AT vsy[9], AT rho0, AT &rR, AT &rB) {
-    rR = AT(0);
-    rB = AT(0);
-#pragma unroll
-    for (int a = 0; a < 9; a++) {
-        const AT fa = wgt<AT>(a) * rho0 + d[a];
-        const AT t = wgt<AT>(a) * (AT(EX[a]) * vsx[a] + AT(EY[a]) * vsy[a]);
-        rR += cs[a] * fa + t;
-        rB += (AT(1) - cs[a]) * fa - t;
-    }
+__device__ __forceinline__ void collide(const DomDev &D, const AT d[9], AT Fx, AT Fy, AT rN,
+                                        AT o[9], AT &rho_out, AT &ux_out, AT &uy_out) {
+    const AT rho0 = AT(D.rho0);
+    const AT drho = d[0] + d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8];
+    const AT sa = d[1] + d[2] + d[3] + d[4];
+    const AT sd = d[5] + d[6] + d[7] + d[8];
+    const AT jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
+    const AT jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
+    const AT m1 = AT(-4) * d[0] - sa + AT(2) * sd;
+    const AT m2 = AT(4) * d[0] - AT(2) * sa + sd;
+    const AT m4 = AT(-2) * (d[1] - d[3]) + (d[5] - d[6] - d[7] + d[8]);
+    const AT m6 = AT(-2) * (d[2] - d[4]) + (d[5] + d[6] - d[7] - d[8]);
+    const AT m7 = d[1] - d[2] + d[3] - d[4];
+    const AT m8 = d[5] - d[6] + d[7] - d[8];
+
+    const AT rho = rho0 + drho;
+    const AT inv_rho = rcp(rho);
+    const AT ux = (jx + AT(0.5) * Fx) * inv_rho;
+    const AT uy = (jy + AT(0.5) * Fy) * inv_rho;
+    // Eqs. 18 and 5: 1/nu interpolated in rho^N, tau = 3 nu + 1/2, s_nu = 1/tau
+    const AT inv_nu = (AT(1) + rN) * AT(D.inv2nu_r) + (AT(1) - rN) * AT(D.inv2nu_b);
+    const AT sv = inv_nu * rcp(AT(3) + AT(0.5) * inv_nu);
+    const AT se = AT(D.s_e), seps = AT(D.s_eps), sq = AT(D.s_q);
+
+    const AT uu = ux * ux + uy * uy;
+    const AT r3uu = AT(3) * rho * uu;
+    const AT uF = ux * Fx + uy * Fy;
+    const AT p0 = drho;
+    const AT p1 = m1 - se * (m1 + AT(2) * drho - r3uu) + (AT(1) - AT(0.5) * se) * (AT(6) * uF);
+    const AT p2 = m2 - seps * (m2 - drho + r3uu) - (AT(1) - AT(0.5) * seps) * (AT(6) * uF);
+    const AT p3 = rho * ux + AT(0.5) * Fx;
+    const AT p4 = m4 - sq * (m4 + rho * ux) - (AT(1) - AT(0.5) * sq) * Fx;
+    const AT p5 = rho * uy + AT(0.5) * Fy;
+    const AT p6 = m6 - sq * (m6 + rho * uy) - (AT(1) - AT(0.5) * sq) * Fy;
+    const AT p7 = m7 - sv * (m7 - rho * (ux * ux - uy * uy)) +
+                  (AT(1) - AT(0.5) * sv) * (AT(2) * (ux * Fx - uy * Fy));
+    const AT p8 = m8 - sv * (m8 - rho * ux * uy) + (AT(1) - AT(0.5) * sv) * (ux * Fy + uy * Fx);
+    // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+    const AT a0 = p0 * AT(1.0 / 9.0), a1 = p1 * AT(1.0 / 36.0), a2 = p2 * AT(1.0 / 36.0);
+    const AT a3 = p3 * AT(1.0 / 6.0), a4 = p4 * AT(1.0 / 12.0);
+    const AT a5 = p5 * AT(1.0 / 6.0), a6 = p6 * AT(1.0 / 12.0);
+    const AT a7 = p7 * AT(0.25), a8 = p8 * AT(0.25);
+    o[0] = a0 - AT(4) * a1 + AT(4) * a2;
+    const AT ax = a0 - a1 - AT(2) * a2;
+    o[1] = ax + a3 - AT(2) * a4 + a7;
+    o[2] = ax + a5 - AT(2) * a6 - a7;
+    o[3] = ax - a3 + AT(2) * a4 + a7;
+    o[4] = ax - a5 + AT(2) * a6 - a7;
+    const AT ad = a0 + AT(2) * a1 + a2;
+    o[5] = ad + a3 + a4 + a5 + a6 + a8;
+    o[6] = ad - a3 - a4 + a5 + a6 - a8;
+    o[7] = ad - a3 - a4 - a5 - a6 + a8;
+    o[8] = ad + a3 + a4 - a5 - a6 - a8;
+    rho_out = rho;
+    ux_out = ux;
+    uy_out = uy;
+}
+
+// Work item of block b: blocks are dealt round-robin to the 8 XCDs, so give each XCD a
+// contiguous run of items (adjacent strips of a domain share halo columns in its L2).
+__device__ __forceinline__ int item_of_block(int b, int n) {
+    const int q = n >> 3, rem = n & 7, xcd = b & 7, k = b >> 3;
+    return xcd * q + min(xcd, rem) + k;
 }
 
 // --------------------------------------------------------------------- step kernel
-template <class T>
-__global__ __launch_bounds__(TILE_LANES *TILE_WAVES) void step_kernel(
-    const StepArgs<T, typename Codec<T>::AT> A) {
+// R wavefronts per block, one tile row each; stage E runs R rows behind stage A (one loop
+// iteration), on the thread that gathered the row.  Stage lags: A +R, B +R-1, C +R-2, D +R-3,
+// E 0.  LDS rings hold 2R rows.
+template <class T, int R>
+__global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ? 4 : 2) void step_kernel(const StepArgs<T, typename Codec<T>::AT> A) {
     using AT = typename Codec<T>::AT;
-    __shared__ AT s_rn[RING][TILE_LANES];
-    __shared__ AT s_nx[RING][TILE_LANES], s_ny[RING][TILE_LANES];
-    __shared__ AT s_gx[RING][TILE_LANES], s_gy[RING][TILE_LANES];
-    __shared__ uint16_t s_m[RING][TILE_LANES];
+    constexpr int Q = 2 * R;
+    __shared__ AT s_rn[Q][TILE_LANES];
+    __shared__ AT s_nx[Q][TILE_LANES], s_ny[Q][TILE_LANES];
+    __shared__ AT s_gx[Q][TILE_LANES], s_gy[Q][TILE_LANES];
+    __shared__ AT s_c[Q][TILE_LANES], s_vx[Q][TILE_LANES], s_vy[Q][TILE_LANES];
+    __shared__ uint16_t s_m[Q][TILE_LANES];
 
-    const WorkItem it = A.items[blockIdx.x];
+    const WorkItem it = A.items[item_of_block(blockIdx.x, A.n_items)];
     const DomDev &D = A.doms[it.dom];
     const int w = threadIdx.x / TILE_LANES;
     const int lane = threadIdx.x % TILE_LANES;
     const int base = it.x0 - HALO;
-    const int X = base + lane;  // raw column of this lane
-    int xe, lm, lp;             // node column, LDS lanes of the x-1 / x+1 stencil neighbours
+    const int X = base + lane;
+    int xe, lm, lp;  // node column; LDS lanes of its x-1 / x+1 stencil neighbours
     if (D.open_x) {
         xe = min(max(X, 0), D.nx - 1);
         lm = max(xe - 1, 0) - base;
@@ -242,44 +399,99 @@ __global__ __launch_bounds__(TILE_LANES *TILE_WAVES) void step_kernel(
     }
     const int lanes_of[3] = {lm, lane, lp};
     const bool out_lane = lane >= HALO && lane < TILE_LANES - HALO && X < D.nx;
-
-    const AT rho0 = AT(D.rho0);
     const AT eps = AT(D.eps);
+    const int y0 = it.y0, y1 = it.y1;
+    const int r_first = y0 - HALO + 1 - R;  // first A row is y0 - 4
 
-    // Stage E of iteration r collides the row this thread gathered in stage A of iteration
-    // r - 4; stage A of iteration r already gathers the next row, hence two register sets.
+    // prefetched inputs of the next stage A row: pulled populations, class word, colour row + 1
+    T pf[9];
+    uint32_t pm = SELF_SOLID;
+    AT pc = AT(0), pvx = AT(0), pvy = AT(0);
+
+    auto row_ok_a = [&](int y) { return y >= y0 - HALO + 1 && y < y1 + HALO - 1; };
+    auto row_ok_c = [&](int y) { return y >= y0 - HALO && y < y1 + HALO; };
+    const uint32_t P = (uint32_t)A.plane;
+    auto prefetch = [&](int ya) {
+        pm = SELF_SOLID;
+        if (row_ok_a(ya)) {
+            const int yw = wrap(ya, D.ny);
+            const Nbr nb = make_nbr(D, xe, yw);
+            pm = Plane<uint16_t>(A.mask, P).load((uint32_t)(nb.row[1] + xe));
+#pragma unroll
+            for (int a = 0; a < 9; a++) {
+                const uint32_t src = (uint32_t)(A.own ? nb.row[1] + xe : pull_src(nb, a));
+                pf[a] = Plane<T>(A.fin + a * A.plane, P).load(src);
+            }
+        }
+        const int yc = ya + 1;
+        if (row_ok_c(yc)) {
+            const uint32_t nd = (uint32_t)D.off + (uint32_t)wrap(yc, D.ny) * (uint32_t)D.nx + xe;
+            pc = Plane<AT>(A.cin, P).load(nd);
+            pvx = Plane<AT>(A.vxin, P).load(nd);
+            pvy = Plane<AT>(A.vyin, P).load(nd);
+        }
+    };
+    auto put_colour = [&](int yc) {
+        const int sl = yc & (Q - 1);
+        s_c[sl][lane] = pc;
+        s_vx[sl][lane] = pvx;
+        s_vy[sl][lane] = pvy;
+    };
+
+    // prologue: colour rows r_first + R - 1 .. r_first + 2R and the first A row's inputs
+    if (w < 2) {
+        const int yc = r_first + R - 1 + w;
+        if (row_ok_c(yc)) {
+            const uint32_t nd = (uint32_t)D.off + (uint32_t)wrap(yc, D.ny) * (uint32_t)D.nx + xe;
+            pc = Plane<AT>(A.cin, P).load(nd);
+            pvx = Plane<AT>(A.vxin, P).load(nd);
+            pvy = Plane<AT>(A.vyin, P).load(nd);
+        }
+        put_colour(yc);
+    }
+    prefetch(r_first + R + w);
+    put_colour(r_first + R + 1 + w);
+    __syncthreads();
+
     AT d[9], dn[9];
     AT rR = AT(0), rB = AT(0), rN = AT(0), rRn = AT(0), rBn = AT(0), rNn = AT(0);
 #pragma unroll
     for (int a = 0; a < 9; a++) d[a] = dn[a] = AT(0);
 
-    const int y0 = it.y0, y1 = it.y1;
-    for (int r = y0 - 2 * HALO; r < y1; r += TILE_WAVES) {
+    for (int r = r_first; r < y1; r += R) {
         // ---- A: gather, densities, colour indicator
         {
-            const int ya = r + HALO + w;
-            uint32_t m = SELF_SOLID;
+            const int ya = r + R + w;
+            const int sl = ya & (Q - 1);
+            const uint32_t m = pm;
             AT rn = AT(0);
-            if (ya >= y0 - HALO && ya < y1 + HALO) {
+            if (lane >= 1 && lane < TILE_LANES - 1 && !(m & SELF_SOLID)) {
                 const int yw = wrap(ya, D.ny);
-                m = A.mask[node_at(D, xe, yw)];
-                if (!(m & SELF_SOLID)) {
-                    AT cs[9], vsx[9], vsy[9];
-                    gather(A, D, xe, yw, m, true, dn, cs, vsx, vsy);
-                    colour_densities(dn, cs, vsx, vsy, rho0, rRn, rBn);
-                    rn = (rRn - rBn) / (rRn + rBn);
-                    rNn = rn;
-                }
+                const Nbr nb = make_nbr(D, xe, yw);
+#pragma unroll
+                for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(pf[a], D.inv_scale[a]);
+                finish_gather(A, D, xe, yw, m, nb, true, dn, rRn, rBn,
+                              [&](int a, AT &c, AT &vx, AT &vy) {
+                                  const int s2 = (ya - EY[a]) & (Q - 1);
+                                  const int l2 = lanes_of[1 - EX[a]];
+                                  c = s_c[s2][l2];
+                                  vx = s_vx[s2][l2];
+                                  vy = s_vy[s2][l2];
+                              });
+                rn = colour_indicator(rRn, rBn);
+                rNn = rn;
             }
-            s_m[ya & (RING - 1)][lane] = (uint16_t)m;
-            s_rn[ya & (RING - 1)][lane] = rn;
+            s_m[sl][lane] = (uint16_t)m;
+            s_rn[sl][lane] = rn;
         }
+        // inputs of the next iteration's stage A row, in flight during stages B-E
+        prefetch(r + 2 * R + w);
         __syncthreads();
-        // ---- B: virtual colour indicator on outermost solid nodes
+        // ---- B: virtual colour indicator on outermost solid nodes (Eq. 29)
         {
-            const int yb = r + HALO - 1 + w;
-            const int sl = yb & (RING - 1);
-            if (lane >= 1 && lane < TILE_LANES - 1 && yb >= y0 - HALO + 1 && yb < y1 + HALO - 1) {
+            const int yb = r + R - 1 + w;
+            const int sl = yb & (Q - 1);
+            if (lane >= 2 && lane < TILE_LANES - 2 && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
                 const uint32_t m = s_m[sl][lane];
                 if (m & SOLID_BND) {
                     AT num = AT(0), den = AT(0);
@@ -287,41 +499,39 @@ __global__ __launch_bounds__(TILE_LANES *TILE_WAVES) void step_kernel(
                     for (int a = 1; a < 9; a++) {
                         if (m & (1u << (a - 1))) continue;
                         const AT wa = wgt<AT>(a);
-                        num += wa * s_rn[(yb + EY[a]) & (RING - 1)][lanes_of[EX[a] + 1]];
+                        num += wa * s_rn[(yb + EY[a]) & (Q - 1)][lanes_of[EX[a] + 1]];
                         den += wa;
                     }
-                    s_rn[sl][lane] = num / den;
+                    s_rn[sl][lane] = num * rcp(den);
                 }
             }
         }
         __syncthreads();
-        // ---- C: colour gradient, wetting correction, interface normal
+        // ---- C: colour gradient (Eq. 28), wetting correction, interface normal (Eq. 22)
         {
-            const int yc = r + HALO - 2 + w;
-            const int sl = yc & (RING - 1);
-            if (lane >= 2 && lane < TILE_LANES - 2 && yc >= y0 - HALO + 2 && yc < y1 + HALO - 2) {
+            const int yc = r + R - 2 + w;
+            const int sl = yc & (Q - 1);
+            if (lane >= 3 && lane < TILE_LANES - 3 && yc >= y0 - HALO + 3 && yc < y1 + HALO - 3) {
                 const uint32_t m = s_m[sl][lane];
                 AT gx = AT(0), gy = AT(0), nx = AT(0), ny = AT(0);
                 if (!(m & SELF_SOLID)) {
-#pragma clang fp contract(off)
-                    AT sx = AT(0), sy = AT(0);
+                    {
+                        AT sx = AT(0), sy = AT(0);
 #pragma unroll
-                    for (int a = 1; a < 9; a++) {
-                        const AT v = s_rn[(yc + EY[a]) & (RING - 1)][lanes_of[EX[a] + 1]];
-                        if (EX[a]) sx += wgt<AT>(a) * v * AT(EX[a]);
-                        if (EY[a]) sy += wgt<AT>(a) * v * AT(EY[a]);
+                        for (int a = 1; a < 9; a++) {
+                            const AT v = s_rn[(yc + EY[a]) & (Q - 1)][lanes_of[EX[a] + 1]];
+                            if (EX[a]) sx = acc_nc(sx, wgt<AT>(a), v, EX[a]);
+                            if (EY[a]) sy = acc_nc(sy, wgt<AT>(a), v, EY[a]);
+                        }
+                        gx = AT(3) * sx;
+                        gy = AT(3) * sy;
                     }
-                    gx = AT(3) * sx;
-                    gy = AT(3) * sy;
                     if (m & FLUID_BND) {
-                        const size_t nd = node_at(D, xe, wrap(yc, D.ny));
+                        const size_t nd = (size_t)D.off + (size_t)wrap(yc, D.ny) * D.nx + xe;
                         wetting_correct(A.nsx[nd], A.nsy[nd], AT(D.cos_t), AT(D.sin_t), eps, gx, gy);
                     }
-                    const AT g = sqrt(gx * gx + gy * gy);
-                    if (g > eps) {
-                        nx = gx / g;
-                        ny = gy / g;
-                    }
+                    const AT g = fsqrt(gx * gx + gy * gy);
+                    if (g > eps) unit_normal(gx, gy, g, nx, ny);
                 }
                 s_gx[sl][lane] = gx;
                 s_gy[sl][lane] = gy;
@@ -330,11 +540,11 @@ __global__ __launch_bounds__(TILE_LANES *TILE_WAVES) void step_kernel(
             }
         }
         __syncthreads();
-        // ---- D: virtual interface normals on outermost solid nodes
+        // ---- D: virtual interface normals on outermost solid nodes (Eq. 29, second BC)
         {
-            const int yd = r + HALO - 3 + w;
-            const int sl = yd & (RING - 1);
-            if (lane >= 3 && lane < TILE_LANES - 3 && yd >= y0 - 1 && yd < y1 + 1) {
+            const int yd = r + R - 3 + w;
+            const int sl = yd & (Q - 1);
+            if (lane >= 4 && lane < TILE_LANES - 4 && yd >= y0 - 1 && yd < y1 + 1) {
                 const uint32_t m = s_m[sl][lane];
                 if (m & SOLID_BND) {
                     AT numx = AT(0), numy = AT(0), den = AT(0);
@@ -342,114 +552,64 @@ __global__ __launch_bounds__(TILE_LANES *TILE_WAVES) void step_kernel(
                     for (int a = 1; a < 9; a++) {
                         if (m & (1u << (a - 1))) continue;
                         const AT wa = wgt<AT>(a);
-                        const int s2 = (yd + EY[a]) & (RING - 1);
+                        const int s2 = (yd + EY[a]) & (Q - 1);
                         const int l2 = lanes_of[EX[a] + 1];
                         numx += wa * s_nx[s2][l2];
                         numy += wa * s_ny[s2][l2];
                         den += wa;
                     }
-                    s_nx[sl][lane] = numx / den;
-                    s_ny[sl][lane] = numy / den;
+                    const AT iden = rcp(den);
+                    s_nx[sl][lane] = numx * iden;
+                    s_ny[sl][lane] = numy * iden;
                 }
             }
+            // colour row for the next iteration's stage A (its loads were issued after A)
+            put_colour(r + 2 * R + 1 + w);
         }
         __syncthreads();
-        // ---- E: curvature, force, collision, recolouring state, store
+        // ---- E: curvature (Eq. 13), force (Eq. 10), collision, recolouring state (Eq. 14)
         {
             const int ye = r + w;
-            const int sl = ye & (RING - 1);
+            const int sl = ye & (Q - 1);
             if (out_lane && ye >= y0 && ye < y1 && !(s_m[sl][lane] & SELF_SOLID)) {
                 AT dxnx = AT(0), dynx = AT(0), dxny = AT(0), dyny = AT(0);
                 {
-#pragma clang fp contract(off)
 #pragma unroll
-                for (int a = 1; a < 9; a++) {
-                    const int s2 = (ye + EY[a]) & (RING - 1);
-                    const int l2 = lanes_of[EX[a] + 1];
-                    const AT vx = s_nx[s2][l2], vy = s_ny[s2][l2];
-                    if (EX[a]) {
-                        dxnx += wgt<AT>(a) * vx * AT(EX[a]);
-                        dxny += wgt<AT>(a) * vy * AT(EX[a]);
+                    for (int a = 1; a < 9; a++) {
+                        const int s2 = (ye + EY[a]) & (Q - 1);
+                        const int l2 = lanes_of[EX[a] + 1];
+                        const AT vx = s_nx[s2][l2], vy = s_ny[s2][l2];
+                        if (EX[a]) {
+                            dxnx += wgt<AT>(a) * vx * AT(EX[a]);
+                            dxny += wgt<AT>(a) * vy * AT(EX[a]);
+                        }
+                        if (EY[a]) {
+                            dynx += wgt<AT>(a) * vx * AT(EY[a]);
+                            dyny += wgt<AT>(a) * vy * AT(EY[a]);
+                        }
                     }
-                    if (EY[a]) {
-                        dynx += wgt<AT>(a) * vx * AT(EY[a]);
-                        dyny += wgt<AT>(a) * vy * AT(EY[a]);
-                    }
-                }
-                dxnx *= AT(3);
-                dynx *= AT(3);
-                dxny *= AT(3);
-                dyny *= AT(3);
+                    dxnx *= AT(3);
+                    dynx *= AT(3);
+                    dxny *= AT(3);
+                    dyny *= AT(3);
                 }
                 const AT nx = s_nx[sl][lane], ny = s_ny[sl][lane];
                 const AT gx = s_gx[sl][lane], gy = s_gy[sl][lane];
                 const AT kappa = -nx * nx * dyny - ny * ny * dxnx + nx * ny * (dynx + dxny);
                 const AT Fx = AT(D.half_sigma) * kappa * gx;
                 const AT Fy = AT(D.half_sigma) * kappa * gy;
-
-                // moments of the deviations
-                const AT drho = d[0] + d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8];
-                const AT sa = d[1] + d[2] + d[3] + d[4];
-                const AT sd = d[5] + d[6] + d[7] + d[8];
-                const AT jx = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
-                const AT jy = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
-                const AT m1 = AT(-4) * d[0] - sa + AT(2) * sd;
-                const AT m2 = AT(4) * d[0] - AT(2) * sa + sd;
-                const AT m4 = AT(-2) * (d[1] - d[3]) + (d[5] - d[6] - d[7] + d[8]);
-                const AT m6 = AT(-2) * (d[2] - d[4]) + (d[5] + d[6] - d[7] - d[8]);
-                const AT m7 = d[1] - d[2] + d[3] - d[4];
-                const AT m8 = d[5] - d[6] + d[7] - d[8];
-
-                const AT rho = rho0 + drho;
-                const AT ux = (jx + AT(0.5) * Fx) / rho;
-                const AT uy = (jy + AT(0.5) * Fy) / rho;
-                const AT inv_nu = (AT(1) + rN) * AT(D.inv2nu_r) + (AT(1) - rN) * AT(D.inv2nu_b);
-                const AT nu = AT(1) / inv_nu;
-                const AT sv = AT(1) / (AT(3) * nu + AT(0.5));
-                const AT se = AT(D.s_e), seps = AT(D.s_eps), sq = AT(D.s_q);
-
-                const AT uu = ux * ux + uy * uy;
-                const AT r3uu = AT(3) * rho * uu;
-                const AT uF = ux * Fx + uy * Fy;
-                // post-collision moments of the deviations (Eqs. 1, 2, 8 in moment space)
-                const AT p0 = drho;
-                const AT p1 = m1 - se * (m1 + AT(2) * drho - r3uu) + (AT(1) - AT(0.5) * se) * (AT(6) * uF);
-                const AT p2 = m2 - seps * (m2 - drho + r3uu) - (AT(1) - AT(0.5) * seps) * (AT(6) * uF);
-                const AT p3 = rho * ux + AT(0.5) * Fx;
-                const AT p4 = m4 - sq * (m4 + rho * ux) - (AT(1) - AT(0.5) * sq) * Fx;
-                const AT p5 = rho * uy + AT(0.5) * Fy;
-                const AT p6 = m6 - sq * (m6 + rho * uy) - (AT(1) - AT(0.5) * sq) * Fy;
-                const AT p7 = m7 - sv * (m7 - rho * (ux * ux - uy * uy)) +
-                              (AT(1) - AT(0.5) * sv) * (AT(2) * (ux * Fx - uy * Fy));
-                const AT p8 = m8 - sv * (m8 - rho * ux * uy) + (AT(1) - AT(0.5) * sv) * (ux * Fy + uy * Fx);
-                // back to populations: M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-                const AT a0 = p0 * AT(1.0 / 9.0), a1 = p1 * AT(1.0 / 36.0), a2 = p2 * AT(1.0 / 36.0);
-                const AT a3 = p3 * AT(1.0 / 6.0), a4 = p4 * AT(1.0 / 12.0);
-                const AT a5 = p5 * AT(1.0 / 6.0), a6 = p6 * AT(1.0 / 12.0);
-                const AT a7 = p7 * AT(0.25), a8 = p8 * AT(0.25);
-                AT o[9];
-                o[0] = a0 - AT(4) * a1 + AT(4) * a2;
-                const AT ax = a0 - a1 - AT(2) * a2;
-                o[1] = ax + a3 - AT(2) * a4 + a7;
-                o[2] = ax + a5 - AT(2) * a6 - a7;
-                o[3] = ax - a3 + AT(2) * a4 + a7;
-                o[4] = ax - a5 + AT(2) * a6 - a7;
-                const AT ad = a0 + AT(2) * a1 + a2;
-                o[5] = ad + a3 + a4 + a5 + a6 + a8;
-                o[6] = ad - a3 - a4 + a5 + a6 - a8;
-                o[7] = ad - a3 - a4 - a5 - a6 + a8;
-                o[8] = ad + a3 + a4 - a5 - a6 - a8;
-
-                // recolouring state (Eq. 14)
-                const AT rs = rR + rB;
-                const AT c = rR / rs;
-                const AT b = AT(D.beta) * (rR * rB / rs);
-                const size_t nd = node_at(D, xe, wrap(ye, D.ny));
+                AT o[9], rho, ux, uy;
+                collide(D, d, Fx, Fy, rN, o, rho, ux, uy);
+                const AT irs = rcp(rR + rB);
+                const AT c = rR * irs;
+                const AT b = AT(D.beta) * (rR * rB * irs);
+                const uint32_t nd = (uint32_t)D.off + (uint32_t)wrap(ye, D.ny) * (uint32_t)D.nx + xe;
 #pragma unroll
-                for (int a = 0; a < 9; a++) Codec<T>::store(A.fout + a * A.plane + nd, o[a], D.scale[a]);
-                A.cout[nd] = c;
-                A.vxout[nd] = b * nx;
-                A.vyout[nd] = b * ny;
+                for (int a = 0; a < 9; a++)
+                    Plane<T>(A.fout + a * A.plane, P).store(nd, Codec<T>::encode(o[a], D.scale[a]));
+                Plane<AT>(A.cout, P).store(nd, c);
+                Plane<AT>(A.vxout, P).store(nd, b * nx);
+                Plane<AT>(A.vyout, P).store(nd, b * ny);
                 if (!(isfinite(rho) && isfinite(ux) && isfinite(uy))) atomicOr(A.flag, 1);
             }
         }
@@ -458,9 +618,11 @@ __global__ __launch_bounds__(TILE_LANES *TILE_WAVES) void step_kernel(
         rR = rRn;
         rB = rBn;
         rN = rNn;
-        // No barrier here: the next stage A writes ring rows r + 8 .. r + 11 of s_rn / s_m,
-        // which alias rows r .. r + 3.  Of those, stage E reads only s_m of its own row, which
-        // only its own wavefront rewrites; the n and g rings are not touched by stage A.
+        // No barrier here.  The next stage A writes s_m / s_rn rows r + 2R .. r + 3R - 1, which
+        // alias rows r .. r + R - 1; of those, stage E reads only s_m of its own row, written
+        // by its own wavefront.  The colour ring rows written in stage D are read only by the
+        // next stage A (after the D-E barrier), and the n / g rings only change after the
+        // next A-B barrier.
     }
 }
 
@@ -475,26 +637,56 @@ __global__ void read_kernel(const StepArgs<T, typename Codec<T>::AT> A, int dom,
          i += (size_t)gridDim.x * blockDim.x) {
         const int x = (int)(i % D.nx), y = (int)(i / D.nx);
         const uint32_t m = A.mask[D.off + i];
-        double fR[9], fB[9], rR = 0.0, rB = 0.0;
+        double fR[9], fB[9], sR = 0.0, sB = 0.0;
+#pragma unroll
+        for (int a = 0; a < 9; a++) fR[a] = fB[a] = 0.0;
         if (!(m & SELF_SOLID)) {
-            AT d[9], cs[9], vsx[9], vsy[9];
-            gather(A, D, x, y, m, false, d, cs, vsx, vsy);
+            // the step's completion of the populations, then the colour source of each one
+            const Nbr nb = make_nbr(D, x, y);
+            const size_t self = nb.row[1] + x;
+            AT d[9], rR, rB;
+#pragma unroll
+            for (int a = 0; a < 9; a++)
+                d[a] = Codec<T>::load(A.fin + a * A.plane + (A.own ? self : pull_src(nb, a)),
+                                      D.inv_scale[a]);
+            finish_gather(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
+                const size_t src = (a == 0 || A.own) ? self : pull_src(nb, a);
+                c = A.cin[src];
+                vx = A.own ? AT(0) : A.vxin[src];
+                vy = A.own ? AT(0) : A.vyin[src];
+            });
+            const AT cself = A.cin[self];
+            const AT vxs = A.own ? AT(0) : A.vxin[self], vys = A.own ? AT(0) : A.vyin[self];
 #pragma unroll
             for (int a = 0; a < 9; a++) {
+                AT cs, vsx, vsy;
+                if (A.own || a == 0) {
+                    cs = cself;
+                    vsx = vsy = AT(0);
+                } else if (pull_outside(nb, a)) {
+                    cs = nb.lo ? AT(1) : cself;  // inlet injects red; outlet keeps the node's
+                    vsx = vsy = AT(0);
+                } else if (m & (1u << (OPP[a] - 1))) {
+                    cs = cself;
+                    vsx = -vxs;
+                    vsy = -vys;
+                } else {
+                    const size_t src = pull_src(nb, a);
+                    cs = A.cin[src];
+                    vsx = A.vxin[src];
+                    vsy = A.vyin[src];
+                }
                 const double fa = wgt<double>(a) * D.rho0 + (double)d[a];
-                const double t = wgt<double>(a) * (EX[a] * (double)vsx[a] + EY[a] * (double)vsy[a]);
-                fR[a] = (double)cs[a] * fa + t;
-                fB[a] = (1.0 - (double)cs[a]) * fa - t;
-                rR += fR[a];
-                rB += fB[a];
+                const double t = wgt<double>(a) * (EX[a] * (double)vsx + EY[a] * (double)vsy);
+                fR[a] = (double)cs * fa + t;
+                fB[a] = (1.0 - (double)cs) * fa - t;
+                sR += fR[a];
+                sB += fB[a];
             }
-        } else {
-#pragma unroll
-            for (int a = 0; a < 9; a++) fR[a] = fB[a] = 0.0;
         }
         size_t p = 0;
-        if (which & 1u) out[(p++) * nn + i] = rR;
-        if (which & 2u) out[(p++) * nn + i] = rB;
+        if (which & 1u) out[(p++) * nn + i] = sR;
+        if (which & 2u) out[(p++) * nn + i] = sB;
         if (which & 4u) {
 #pragma unroll
             for (int a = 0; a < 9; a++) out[(p + a) * nn + i] = fR[a];
@@ -520,14 +712,10 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
          i += (size_t)blocks_per_dom * MASS_THREADS) {
         const uint32_t m = A.mask[D.off + i];
         if (m & SELF_SOLID) continue;
-        AT d[9], cs[9], vsx[9], vsy[9];
-        gather(A, D, (int)(i % D.nx), (int)(i / D.nx), m, false, d, cs, vsx, vsy);
-        for (int a = 0; a < 9; a++) {
-            const double fa = wgt<double>(a) * D.rho0 + (double)d[a];
-            const double t = wgt<double>(a) * (EX[a] * (double)vsx[a] + EY[a] * (double)vsy[a]);
-            sR += (double)cs[a] * fa + t;
-            sB += (1.0 - (double)cs[a]) * fa - t;
-        }
+        AT d[9], rR, rB;
+        gather_global(A, D, (int)(i % D.nx), (int)(i / D.nx), m, d, rR, rB);
+        sR += (double)rR;
+        sB += (double)rB;
     }
     __shared__ double shR[MASS_THREADS], shB[MASS_THREADS];
     shR[threadIdx.x] = sR;
@@ -561,18 +749,21 @@ __global__ void mass_final_kernel(const double *partials, int n_doms, int blocks
 
 // ------------------------------------------------------------------- launchers
 template <class T>
-static hipError_t step_t(const void *args, int n_items, hipStream_t s) {
+static hipError_t step_t(const void *args, int n_items, int waves, hipStream_t s) {
     const auto &A = *static_cast<const StepArgs<T, typename Codec<T>::AT> *>(args);
-    hipLaunchKernelGGL(step_kernel<T>, dim3(n_items), dim3(TILE_LANES * TILE_WAVES), 0, s, A);
+    if (waves == 8)
+        hipLaunchKernelGGL((step_kernel<T, 8>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
+    else
+        hipLaunchKernelGGL((step_kernel<T, 4>), dim3(n_items), dim3(TILE_LANES * 4), 0, s, A);
     return hipGetLastError();
 }
 
-hipError_t launch_step(int storage, const void *args, int n_items, int, hipStream_t s) {
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (storage) {
-        case 0: return step_t<double>(args, n_items, s);
-        case 1: return step_t<float>(args, n_items, s);
-        case 2: return step_t<__half>(args, n_items, s);
+        case 0: return step_t<double>(args, n_items, waves, s);
+        case 1: return step_t<float>(args, n_items, waves, s);
+        case 2: return step_t<__half>(args, n_items, waves, s);
     }
     return hipErrorInvalidValue;
 }

@@ -43,11 +43,12 @@ PROTOTYPES = {
                                   C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "lbm_create": (C.c_int, [C.POINTER(DomainDesc), C.c_int, C.c_int, C.c_void_p, C.c_size_t,
                              C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbm_classify": (C.c_int, [C.POINTER(DomainDesc), C.POINTER(C.c_uint8), _dp]),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int64]),
     "lbm_read_fields": (C.c_int, [C.c_void_p, C.c_int, C.c_uint32, C.c_void_p, C.c_size_t]),
     "lbm_mass": (C.c_int, [C.c_void_p, _dp]),
     "lbm_steps_taken": (C.c_int64, [C.c_void_p]),
-    "lbm_set_chunk_rows": (C.c_int, [C.c_void_p, C.c_int]),
+    "lbm_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "lbm_state_size": (C.c_size_t, [C.c_void_p]),
     "lbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -59,9 +60,13 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load liblbmcg.so and declare its prototypes (no device work; works without a GPU)."""
+    """Load liblbmcg.so and declare its prototypes (no device work; works without a GPU).
+
+    torch is imported first so that the library binds to the HIP runtime torch has loaded: the
+    device buffers and the stream handed to the library come from that runtime instance."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (load order: torch's HIP runtime first)
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build it with python -m paper_1707_00198_amd.build")
         L = C.CDLL(path)
@@ -158,8 +163,8 @@ class Lattice:
     def steps(self) -> int:
         return int(load_library().lbm_steps_taken(self._h))
 
-    def set_chunk_rows(self, rows: int):
-        _check(load_library().lbm_set_chunk_rows(self._h, int(rows)))
+    def set_tile(self, chunk_rows: int = 0, waves: int = 0):
+        _check(load_library().lbm_set_tile(self._h, int(chunk_rows), int(waves)))
 
     def synchronize(self):
         self.stream.synchronize()

@@ -108,14 +108,16 @@ def droplet_flat(nx=200, h=100, radius=30.0, theta_deg=60.0, nu_r=1.0 / 6.0, nu_
     return Setup(name, solid, rr, rb, p, meta=dict(wall_y=0.5, xc=xc, yc=yc, radius=radius))
 
 
-def droplet_box(theta_deg=60.0, M=1.0, nx=160, ny=100, radius=45.0, nu_r=0.35, sigma=0.02):
+def droplet_box(theta_deg=60.0, M=1.0, nx=160, ny=100, radius=45.0, nu_r=0.35, sigma=0.02,
+                xc_offset=0.0):
     """Flat-wall droplet of Table I: closed nx x ny box (solid frame), radius 45, centre
-    (nx/2, 3/2 - R cos(theta)) in the paper's 1-based indices, nu_R = 0.35, sigma = 0.02."""
+    (nx/2, 3/2 - R cos(theta)) in the paper's 1-based indices, nu_R = 0.35, sigma = 0.02.
+    xc_offset moves the centre off the box's mirror axis."""
     solid = np.zeros((ny, nx), dtype=np.uint8)
     solid[0, :] = solid[-1, :] = 1
     solid[:, 0] = solid[:, -1] = 1
     x, y = _grid(ny, nx)
-    xc = nx / 2.0 - 1.0
+    xc = nx / 2.0 - 1.0 + xc_offset
     yc = 0.5 - radius * math.cos(math.radians(theta_deg))
     red = (x - xc) ** 2 + (y - yc) ** 2 <= radius ** 2
     rr, rb = _colour_fields(solid, red)

@@ -99,3 +99,40 @@ def test_lattice_refuses_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         lbm.Lattice([W.cfg_droplet_flat()])
+
+
+def classify(s):
+    L = lbm.load_library()
+    d, keep = _desc(s)
+    if s.ns is not None:
+        ns = np.ascontiguousarray(s.ns, dtype=np.float64)
+        keep.append(ns)
+        d.ns = ns.ctypes.data_as(C.POINTER(C.c_double))
+    cls = np.empty((s.ny, s.nx), np.uint8)
+    nrm = np.empty((s.ny, s.nx, 2))
+    rc = L.lbm_classify(C.byref(d), cls.ctypes.data_as(C.POINTER(C.c_uint8)),
+                        nrm.ctypes.data_as(C.POINTER(C.c_double)))
+    assert rc == 0, L.lbm_last_error()
+    return cls, nrm
+
+
+def _classify_cases():
+    import test_gpu_parity as T
+    out = list(T.ragged_cases())
+    out += [W.cylinder_droplet(n=96, rc=20.0, rd=18.0, theta_deg=120.0, ccx=48.0, ccy=30.0),
+            W.cylinder_droplet(n=64, rc=12.0, rd=10.0, analytic_normals=True, ccx=32.0, ccy=20.0),
+            W.capillary(nx=120, ny=30, plate_x0=30, plate_x1=90, thick=5, blue_x0=40, blue_x1=100),
+            W.fingering_channel(nx=80, h=12), W.droplet_box(nx=40, ny=30, radius=10.0)]
+    return out
+
+
+@pytest.mark.parametrize("idx", range(13))
+def test_library_classification_matches_oracle(idx):
+    """Node classes and wall normals (Eqs. 32-33 or analytic) computed by the library's host
+    runtime equal the oracle's, bit for bit."""
+    import oracle
+    s = _classify_cases()[idx]
+    cls, nrm = classify(s)
+    o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **s.oracle_kwargs())
+    assert np.array_equal(cls, o.classes())
+    assert np.array_equal(nrm, o.wall_normals())

@@ -285,3 +285,19 @@ def test_piston_displacement_speed_at_high_viscosity_ratio():
     m1 = physics.finger_metrics(o.field("rhoN"), s.solid)
     speed = (m1["contact_line"] - m0["contact_line"]) / 3000.0
     assert abs(speed / (2.0 / 3.0 * u0) - 1.0) < 0.05
+
+
+def test_eq36_ties_at_exact_mirror_symmetry():
+    """The contact-angle selection (Eq. 36) is discontinuous.  On a mirror axis the estimated
+    direction at a wall node is parallel to the wall normal, so D1 == D2 in exact arithmetic and
+    rounding decides; the oracle and its own mirror-image run (same arithmetic, mirrored
+    summation order) then part visibly.  Off the axis they agree to roundoff."""
+    def mirror_gap(s, steps=200):
+        kw = s.oracle_kwargs()
+        a = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **kw).step(steps).pops()
+        b = oracle.Oracle(s.solid[:, ::-1], s.rho_r0[:, ::-1], s.rho_b0[:, ::-1],
+                          **kw).step(steps).pops()
+        return np.abs(a - b[:, :, :, ::-1][:, MIRROR_X]).max()
+    assert mirror_gap(W.droplet_box(theta_deg=150.0, M=10.0, nx=70, ny=50, radius=16.0)) > 1e-6
+    assert mirror_gap(W.droplet_box(theta_deg=150.0, M=10.0, nx=70, ny=50, radius=16.0,
+                                    xc_offset=0.37)) < 1e-12
