@@ -34,8 +34,8 @@ ARITH = {"f64": "f64", "f32": "f32", "f16": "f32"}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "fingering_large", "fingering", "droplet"])
     ap.add_argument("--storage", default=None, choices=["f64", "f32", "f16"])
@@ -43,7 +43,28 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk-rows", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 2 GiB read + 2 GiB write elementwise kernel, the "
+                         "reference for scaling HBM byte counters")
+    ap.add_argument("--traffic", default=None,
+                    help="profile summary with measured HBM bytes per launch of the step kernel "
+                         "(default: profiles/step_kernel_<workload>_<storage>_hbm_bytes.md)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """Plain elementwise kernel of known traffic: reads 2 GiB and writes 2 GiB (fp32 x * 1)."""
+    import torch
+    n = 512 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 launches of {n * 4} bytes read + {n * 4} bytes written",
+          flush=True)
+    del x, y
+    torch.cuda.empty_cache()
 
 
 def build_workload(name):
@@ -84,6 +105,24 @@ def time_lattice(setups, storage, steps, warmup, chunk_rows=0):
                 ms_per_step=ev_ms / steps, mass=mass)
 
 
+def measured_traffic(path, workload, storage):
+    """HBM bytes per launch from a committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by
+    a copy kernel), or None if there is none or the kernel source has changed since."""
+    import hashlib
+    import re
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    t = json.loads(m.group(1))
+    src = os.path.join(ROOT, "paper_1707_00198_amd", "csrc", "lbm_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if t.get("kernel_source_sha256") != h or t.get("workload") != workload or t.get("storage") != storage:
+        return None
+    return t.get("bytes_per_launch")
+
+
 def cpu_baseline(seconds):
     """The FP64 oracle, as it is, on one H = 50 channel of the sweep (800 x 52 lattice),
     as many steps as fit in about `seconds`."""
@@ -116,6 +155,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
 
+    if args.calibrate_copy:
+        copy_calibration()
+
     setups, storage, desc = build_workload(args.workload)
     if args.storage:
         storage = args.storage
@@ -138,8 +180,10 @@ def main():
     bpl = BYTES_PER_LUP[storage]
     lups_per_launch = head["fluid"]
     achieved = bpl * lups_per_launch / (head["ms_per_step"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.traffic or os.path.join(
+        ROOT, "profiles", f"step_kernel_{args.workload}_{storage}_hbm_bytes.md"), args.workload, storage)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=f"step_kernel<{ {'f64': 'double', 'f32': 'float', 'f16': '__half'}[storage] }>",
                     bytes_per_lup=bpl, lups_per_launch=lups_per_launch)
 
