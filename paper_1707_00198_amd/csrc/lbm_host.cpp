@@ -344,12 +344,6 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
         D.rho0 = q.rho0;
         D.eps = q.eps;
         D.outlet_u = q.outlet_u;
-        for (int a = 0; a < 9; a++) {
-            float s = 1.0f;
-            if (c->storage == 2) s = std::ldexp(1.0f, (int)std::lround(std::log2(256.0 / WH[a])));
-            D.scale[a] = s;
-            D.inv_scale[a] = 1.0f / s;
-        }
         for (int y = 0; y < q.ny; y++)
             for (int x = 0; x < q.nx; x++) {
                 const size_t k = (size_t)y * q.nx + x, g = off + k;
@@ -361,7 +355,8 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
                 nsy[g] = (AT)vy;
                 if (s) continue;
                 const double rr = q.rho_r0[k], rb = q.rho_b0[k], rho = rr + rb;
-                for (int a = 0; a < 9; a++) f[a * P + g] = encode<T>(WH[a] * (rho - q.rho0), D.scale[a]);
+                for (int a = 0; a < 9; a++)
+                    f[a * P + g] = encode<T>(WH[a] * (rho - q.rho0), c->storage == 2 ? fp16_scale(a) : 1.0f);
                 col[g] = (AT)(rr / rho);
                 if (q.open_x && x == q.nx - 1) {
                     hist[3 * (io + y) + 0] = (AT)(WH[3] * (rho - q.rho0));

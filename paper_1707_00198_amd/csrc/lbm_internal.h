@@ -27,8 +27,10 @@ struct DomDev {
     double inv2nu_r, inv2nu_b;
     double half_sigma, beta, cos_t, sin_t;
     double s_e, s_eps, s_q, rho0, eps, outlet_u;
-    float scale[9], inv_scale[9];
 };
+
+// FP16 storage scale of direction a (the device codec uses the same constants).
+inline float fp16_scale(int a) { return a == 0 ? 512.0f : (a < 5 ? 2048.0f : 8192.0f); }
 
 struct WorkItem {
     int dom, x0, y0, y1;

@@ -48,6 +48,15 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// a / b: IEEE in FP64; in FP32 the 1-ulp reciprocal refined by one Newton step, which removes
+// the reciprocal's systematic bias (the red fraction c = rho_R / rho must not drift the
+// colour masses).
+__device__ __forceinline__ double quotient(double a, double b) { return a / b; }
+__device__ __forceinline__ float quotient(float a, float b) {
+    const float q = a * rcp(b);
+    return fmaf(rcp(b), fmaf(-q, b, a), q);
+}
+
 // Colour indicator (Eq. 12), exactly +-1 in pure phases.
 __device__ __forceinline__ double colour_indicator(double rR, double rB) { return (rR - rB) / (rR + rB); }
 __device__ __forceinline__ float colour_indicator(float rR, float rB) {
@@ -83,40 +92,42 @@ struct Codec;
 template <>
 struct Codec<double> {
     using AT = double;
-    __device__ static double load(const double *p, float) { return *p; }
-    __device__ static double decode(double v, float) { return v; }
-    __device__ static double encode(double v, float) { return v; }
-    __device__ static void store(double *p, double v, float) { *p = v; }
+    __device__ static double load(const double *p, int) { return *p; }
+    __device__ static double decode(double v, int) { return v; }
+    __device__ static double encode(double v, int) { return v; }
 };
 template <>
 struct Codec<float> {
     using AT = float;
-    __device__ static float load(const float *p, float) { return *p; }
-    __device__ static float decode(float v, float) { return v; }
-    __device__ static float encode(float v, float) { return v; }
-    __device__ static void store(float *p, float v, float) { *p = v; }
+    __device__ static float load(const float *p, int) { return *p; }
+    __device__ static float decode(float v, int) { return v; }
+    __device__ static float encode(float v, int) { return v; }
 };
 template <>
 struct Codec<__half> {
     using AT = float;
-    __device__ static float load(const __half *p, float inv_scale) {
-        return __half2float(*p) * inv_scale;
-    }
-    __device__ static float decode(__half v, float inv_scale) { return __half2float(v) * inv_scale; }
-    __device__ static __half encode(float v, float scale) { return __float2half_rn(v * scale); }
-    __device__ static void store(__half *p, float v, float scale) {
-        *p = __float2half_rn(v * scale);
-    }
+    // FP16 holds the deviation times 2^k(a), k = round(log2(256 / w_a)): 2^9, 2^11, 2^13 for
+    // rest, axis and diagonal directions, which keeps typical deviations far from the FP16
+    // subnormal range without risking overflow.
+    __device__ static constexpr float scale(int a) { return a == 0 ? 512.0f : (a < 5 ? 2048.0f : 8192.0f); }
+    __device__ static float load(const __half *p, int a) { return __half2float(*p) * (1.0f / scale(a)); }
+    __device__ static float decode(__half v, int a) { return __half2float(v) * (1.0f / scale(a)); }
+    __device__ static __half encode(float v, int a) { return __float2half_rn(v * scale(a)); }
 };
 
 // Periodic wrap of an index that is usually already in [0, n): one compare on the fast path.
-// Element access into one node plane with a 32-bit index (uniform base pointer).
+// Element access into one node plane: a uniform base pointer plus a 32-bit byte offset, so
+// that each access needs one vector offset (planes are below 2^31 bytes, checked on the host).
 template <class V>
 struct Plane {
     V *p;
     __device__ __forceinline__ Plane(const V *b, uint32_t) : p(const_cast<V *>(b)) {}
-    __device__ __forceinline__ V load(uint32_t i) const { return p[i]; }
-    __device__ __forceinline__ void store(uint32_t i, V v) const { p[i] = v; }
+    __device__ __forceinline__ V load(uint32_t i) const {
+        return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(p) + i * (uint32_t)sizeof(V));
+    }
+    __device__ __forceinline__ void store(uint32_t i, V v) const {
+        *reinterpret_cast<V *>(reinterpret_cast<char *>(p) + i * (uint32_t)sizeof(V)) = v;
+    }
 };
 
 __device__ __forceinline__ int wrap(int v, int n) {
@@ -187,6 +198,19 @@ __device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, const Do
         for (int a = 0; a < 9; a++) tot += wgt<AT>(a) * rho0 + d[a];
         rR = cself * tot;
         rB = tot - rR;
+    } else if ((m & 0xFFu) == 0u && !nb.lo && !nb.hi) {
+        // interior node: every population is pulled from a fluid neighbour
+        AT tot = wgt<AT>(0) * rho0 + d[0];
+        rR = cself * tot;
+#pragma unroll
+        for (int a = 1; a < 9; a++) {
+            AT c, vx, vy;
+            colour(a, c, vx, vy);
+            const AT fa = wgt<AT>(a) * rho0 + d[a];
+            rR += c * fa + wgt<AT>(a) * (AT(EX[a]) * vx + AT(EY[a]) * vy);
+            tot += fa;
+        }
+        rB = tot - rR;
     } else {
         AT cs[9], vsx[9], vsy[9];
         cs[0] = cself;
@@ -197,7 +221,7 @@ __device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, const Do
                 cs[a] = cself;
                 vsx[a] = vsy[a] = AT(0);
             } else if (m & (1u << (OPP[a] - 1))) {  // half-way bounce-back
-                d[a] = Codec<T>::load(A.fin + OPP[a] * A.plane + self, D.inv_scale[OPP[a]]);
+                d[a] = Codec<T>::load(A.fin + OPP[a] * A.plane + self, OPP[a]);
                 cs[a] = cself;
                 vsx[a] = -vxs;
                 vsy[a] = -vys;
@@ -230,8 +254,8 @@ __device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, const Do
                     // post-streaming f_a of the neighbour (x - 1, y): from (x, y - e_y) or bounced
                     const AT inner =
                         (mm & (1u << (OPP[a] - 1)))
-                            ? Codec<T>::load(A.fin + OPP[a] * A.plane + self - 1, D.inv_scale[OPP[a]])
-                            : Codec<T>::load(A.fin + a * A.plane + nb.row[1 - EY[a]] + x, D.inv_scale[a]);
+                            ? Codec<T>::load(A.fin + OPP[a] * A.plane + self - 1, OPP[a])
+                            : Codec<T>::load(A.fin + a * A.plane + nb.row[1 - EY[a]] + x, a);
                     v = (v + U * inner) / (AT(1) + U);
                 }
                 d[a] = v;
@@ -265,7 +289,7 @@ __device__ __forceinline__ void gather_global(const StepArgs<T, AT> &A, const Do
 #pragma unroll
     for (int a = 0; a < 9; a++) {
         const size_t src = A.own ? self : pull_src(nb, a);
-        d[a] = Codec<T>::load(A.fin + a * A.plane + src, D.inv_scale[a]);
+        d[a] = Codec<T>::load(A.fin + a * A.plane + src, a);
     }
     finish_gather(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
         const size_t src = (a == 0 || A.own) ? self : pull_src(nb, a);
@@ -381,8 +405,13 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
     __shared__ AT s_c[Q][TILE_LANES], s_vx[Q][TILE_LANES], s_vy[Q][TILE_LANES];
     __shared__ uint16_t s_m[Q][TILE_LANES];
 
-    const WorkItem it = A.items[item_of_block(blockIdx.x, A.n_items)];
-    const DomDev &D = A.doms[it.dom];
+    // work item and domain parameters: wave-uniform, read once into registers (stores in the
+    // loop could alias them otherwise, forcing reloads)
+    const WorkItem *itp = A.items + item_of_block(blockIdx.x, A.n_items);
+    const int dom = __builtin_amdgcn_readfirstlane(itp->dom);
+    const WorkItem it{dom, __builtin_amdgcn_readfirstlane(itp->x0), __builtin_amdgcn_readfirstlane(itp->y0),
+                      __builtin_amdgcn_readfirstlane(itp->y1)};
+    const DomDev &D = A.doms[dom];
     const int w = threadIdx.x / TILE_LANES;
     const int lane = threadIdx.x % TILE_LANES;
     const int base = it.x0 - HALO;
@@ -469,7 +498,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                 const int yw = wrap(ya, D.ny);
                 const Nbr nb = make_nbr(D, xe, yw);
 #pragma unroll
-                for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(pf[a], D.inv_scale[a]);
+                for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(pf[a], a);
                 finish_gather(A, D, xe, yw, m, nb, true, dn, rRn, rBn,
                               [&](int a, AT &c, AT &vx, AT &vy) {
                                   const int s2 = (ya - EY[a]) & (Q - 1);
@@ -600,13 +629,13 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                 const AT Fy = AT(D.half_sigma) * kappa * gy;
                 AT o[9], rho, ux, uy;
                 collide(D, d, Fx, Fy, rN, o, rho, ux, uy);
-                const AT irs = rcp(rR + rB);
-                const AT c = rR * irs;
-                const AT b = AT(D.beta) * (rR * rB * irs);
+                const AT rs = rR + rB;
+                const AT c = quotient(rR, rs);
+                const AT b = AT(D.beta) * rB * c;
                 const uint32_t nd = (uint32_t)D.off + (uint32_t)wrap(ye, D.ny) * (uint32_t)D.nx + xe;
 #pragma unroll
                 for (int a = 0; a < 9; a++)
-                    Plane<T>(A.fout + a * A.plane, P).store(nd, Codec<T>::encode(o[a], D.scale[a]));
+                    Plane<T>(A.fout + a * A.plane, P).store(nd, Codec<T>::encode(o[a], a));
                 Plane<AT>(A.cout, P).store(nd, c);
                 Plane<AT>(A.vxout, P).store(nd, b * nx);
                 Plane<AT>(A.vyout, P).store(nd, b * ny);
@@ -648,7 +677,7 @@ __global__ void read_kernel(const StepArgs<T, typename Codec<T>::AT> A, int dom,
 #pragma unroll
             for (int a = 0; a < 9; a++)
                 d[a] = Codec<T>::load(A.fin + a * A.plane + (A.own ? self : pull_src(nb, a)),
-                                      D.inv_scale[a]);
+                                      a);
             finish_gather(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
                 const size_t src = (a == 0 || A.own) ? self : pull_src(nb, a);
                 c = A.cin[src];
