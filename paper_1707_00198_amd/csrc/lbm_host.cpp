@@ -264,6 +264,10 @@ void fill_args(const lbm_ctx *c, int parity, StepArgs<T, AT> &A) {
     A.inlet = reinterpret_cast<const AT *>(c->scratch + L.inlet);
     A.plane = L.plane;
     A.flag = reinterpret_cast<int *>(c->scratch + L.flag);
+    A.f_plane_bytes = (uint32_t)(L.plane * sizeof(T));
+    A.f_set_bytes = (uint32_t)(9 * L.plane * sizeof(T));
+    A.c_plane_bytes = (uint32_t)(L.vx_off - L.c_off);
+    A.ns_stride_bytes = (uint32_t)(L.nsy - L.nsx);
 }
 
 // Arguments for the current parity, as raw bytes of the storage's StepArgs instantiation.
@@ -410,8 +414,13 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     int rc = validate(domains, n, storage);
     if (rc) return rc;
     Layout L = make_layout(domains, n, storage);
-    if (L.plane * std::max(storage_bytes(storage), colour_bytes(storage)) >= (size_t(1) << 31))
-        return fail(LBM_EINVAL, "%zu nodes exceed one context's limit of 2^31 bytes per node plane",
+    // The step kernel addresses the 9 population planes, the 3 colour-state planes and the 2
+    // wall-normal planes each as one buffer of fewer than 2^31 bytes.
+    if (L.f_bytes >= (size_t(1) << 31) || 3 * (L.vx_off - L.c_off) >= (size_t(1) << 31) ||
+        2 * (L.nsy - L.nsx) >= (size_t(1) << 31))
+        return fail(LBM_EINVAL,
+                    "%zu nodes exceed one context's limit (2^31 bytes for the 9 population planes "
+                    "and for the 3 colour-state planes); split the domains over several contexts",
                     L.plane);
     if (!state_dev || !scratch_dev) return fail(LBM_EINVAL, "device buffers are NULL");
     if (state_bytes < L.state_bytes || scratch_bytes < L.scratch_bytes)

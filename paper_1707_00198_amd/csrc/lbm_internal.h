@@ -56,6 +56,10 @@ struct StepArgs {
     const AT *inlet;
     size_t plane;
     int *flag;
+    // Byte extents for the step kernel's buffer accesses (each below 2^31, checked on the
+    // host): one population plane, the 9 population planes, one colour-state plane (c, vx and
+    // vy planes follow each other at this stride), and the offset of nsy after nsx.
+    uint32_t f_plane_bytes, f_set_bytes, c_plane_bytes, ns_stride_bytes;
 };
 
 // Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16.

@@ -130,6 +130,11 @@ struct Plane {
     }
 };
 
+// Domain parameters are read through the constant address space: every read is wave-uniform,
+// so it becomes a scalar load, and a reload after vector stores never waits for the vector
+// loads in flight.
+using DomC = const __attribute__((address_space(4))) DomDev;
+
 __device__ __forceinline__ int wrap(int v, int n) {
     if ((unsigned)v < (unsigned)n) return v;
     v %= n;
@@ -145,7 +150,7 @@ struct Nbr {
     bool lo, hi;
 };
 
-__device__ __forceinline__ Nbr make_nbr(const DomDev &D, int x, int y) {
+__device__ __forceinline__ Nbr make_nbr(DomC &D, int x, int y) {
     Nbr n;
     const int ym = y == 0 ? D.ny - 1 : y - 1;
     const int yp = y == D.ny - 1 ? 0 : y + 1;
@@ -181,8 +186,10 @@ __device__ __forceinline__ bool pull_outside(const Nbr &n, int a) {
 // bounce-back on links from solid nodes, Zou-He inlet and convective outlet unknowns; and
 // returns the red and blue densities of Eq. 16.  colour(a, c, vx, vy) yields the colour state
 // of the pull source of direction a (a = 0: the node itself).
-template <class T, class AT, class ColourFn>
-__device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, const DomDev &D, int x, int y,
+// BOUNCED: d[] already holds the bounced populations f_opp(a) of the node itself for pulls from
+// solid nodes (the step kernel's prefetch redirects those loads).
+template <bool BOUNCED, class T, class AT, class ColourFn>
+__device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, DomC &D, int x, int y,
                                               uint32_t m, const Nbr &nb, bool write_hist, AT d[9],
                                               AT &rR, AT &rB, ColourFn colour) {
     const size_t self = nb.row[1] + x;
@@ -221,7 +228,7 @@ __device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, const Do
                 cs[a] = cself;
                 vsx[a] = vsy[a] = AT(0);
             } else if (m & (1u << (OPP[a] - 1))) {  // half-way bounce-back
-                d[a] = Codec<T>::load(A.fin + OPP[a] * A.plane + self, OPP[a]);
+                if (!BOUNCED) d[a] = Codec<T>::load(A.fin + OPP[a] * A.plane + self, OPP[a]);
                 cs[a] = cself;
                 vsx[a] = -vxs;
                 vsy[a] = -vys;
@@ -282,7 +289,7 @@ __device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, const Do
 
 // Gather with colour state from global memory (read-back and reductions).
 template <class T, class AT>
-__device__ __forceinline__ void gather_global(const StepArgs<T, AT> &A, const DomDev &D, int x, int y,
+__device__ __forceinline__ void gather_global(const StepArgs<T, AT> &A, DomC &D, int x, int y,
                                               uint32_t m, AT d[9], AT &rR, AT &rB) {
     const Nbr nb = make_nbr(D, x, y);
     const size_t self = nb.row[1] + x;
@@ -291,7 +298,7 @@ __device__ __forceinline__ void gather_global(const StepArgs<T, AT> &A, const Do
         const size_t src = A.own ? self : pull_src(nb, a);
         d[a] = Codec<T>::load(A.fin + a * A.plane + src, a);
     }
-    finish_gather(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
+    finish_gather<false>(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
         const size_t src = (a == 0 || A.own) ? self : pull_src(nb, a);
         c = A.cin[src];
         vx = A.own ? AT(0) : A.vxin[src];
@@ -326,7 +333,7 @@ __device__ __forceinline__ void wetting_correct(AT nsx, AT nsy, AT ct, AT st, AT
 // MRT collision with Guo forcing (Eqs. 1, 2, 8 in moment space) of the deviations d (f = w rho0
 // + d), force F, local colour indicator rN; returns the post-collision deviations in o.
 template <class AT>
-__device__ __forceinline__ void collide(const DomDev &D, const AT d[9], AT Fx, AT Fy, AT rN,
+__device__ __forceinline__ void collide(DomC &D, const AT d[9], AT Fx, AT Fy, AT rN,
                                         AT o[9], AT &rho_out, AT &ux_out, AT &uy_out) {
     const AT rho0 = AT(D.rho0);
     const AT drho = d[0] + d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8];
@@ -392,29 +399,86 @@ __device__ __forceinline__ int item_of_block(int b, int n) {
 }
 
 // --------------------------------------------------------------------- step kernel
-// R wavefronts per block, one tile row each; stage E runs R rows behind stage A (one loop
-// iteration), on the thread that gathered the row.  Stage lags: A +R, B +R-1, C +R-2, D +R-3,
-// E 0.  LDS rings hold 2R rows.
+// ------------------------------------------------------------------ buffer access
+// The step kernel streams populations and colour state through buffer resources: a uniform
+// descriptor (base, extent below 2^31 bytes), a uniform plane offset and a per-lane byte offset.
+// A lane with nothing to move passes NOWHERE, beyond every extent: the hardware then drops the
+// store, or returns 0 for the load, without touching memory.  Every wavefront thus issues the
+// same vector-memory instructions on every path through a loop iteration, so the compiler can
+// wait for exactly the loads a stage consumes; a skipped store would otherwise leave it
+// counting as if the prefetch were the newest access and wait for every store in flight.
+constexpr uint32_t NOWHERE = 0x80000000u;
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+template <class V>
+struct Buf;
+template <>
+struct Buf<double> {
+    __device__ static double load(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, double v) {
+        using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, 0);
+    }
+};
+template <>
+struct Buf<float> {
+    __device__ static float load(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+    }
+};
+template <>
+struct Buf<__half> {
+    __device__ static __half load(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, __half v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, vo, so, 0);
+    }
+};
+template <>
+struct Buf<uint16_t> {
+    __device__ static uint16_t load(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+    }
+};
+
+// ------------------------------------------------------------------ the step kernel
+// R wavefronts per block, one tile row each.  In iteration r the block runs stages B..E on
+// rows r + R - 1 + w, r + R - 2 + w, r + R - 3 + w and r + w (w = wavefront), then stage A of
+// the next iteration's rows r + 2R + w, and issues the loads for the stage A after that.  Stage E
+// of a row runs on the thread that gathered the row one iteration earlier.  LDS rings hold 2R
+// rows.
 template <class T, int R>
 __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ? 4 : 2) void step_kernel(const StepArgs<T, typename Codec<T>::AT> A) {
     using AT = typename Codec<T>::AT;
     constexpr int Q = 2 * R;
+    constexpr uint32_t SB = sizeof(T), CB = sizeof(AT);
     __shared__ AT s_rn[Q][TILE_LANES];
     __shared__ AT s_nx[Q][TILE_LANES], s_ny[Q][TILE_LANES];
     __shared__ AT s_gx[Q][TILE_LANES], s_gy[Q][TILE_LANES];
     __shared__ AT s_c[Q][TILE_LANES], s_vx[Q][TILE_LANES], s_vy[Q][TILE_LANES];
+    __shared__ AT s_wx[Q][TILE_LANES], s_wy[Q][TILE_LANES];
     __shared__ uint16_t s_m[Q][TILE_LANES];
 
-    // work item and domain parameters: wave-uniform, read once into registers (stores in the
-    // loop could alias them otherwise, forcing reloads)
+    // work item: wave-uniform
     const WorkItem *itp = A.items + item_of_block(blockIdx.x, A.n_items);
     const int dom = __builtin_amdgcn_readfirstlane(itp->dom);
-    const WorkItem it{dom, __builtin_amdgcn_readfirstlane(itp->x0), __builtin_amdgcn_readfirstlane(itp->y0),
-                      __builtin_amdgcn_readfirstlane(itp->y1)};
-    const DomDev &D = A.doms[dom];
+    const int x0 = __builtin_amdgcn_readfirstlane(itp->x0);
+    const int y0 = __builtin_amdgcn_readfirstlane(itp->y0), y1 = __builtin_amdgcn_readfirstlane(itp->y1);
+    DomC &D = *(DomC *)(A.doms + dom);
     const int w = threadIdx.x / TILE_LANES;
     const int lane = threadIdx.x % TILE_LANES;
-    const int base = it.x0 - HALO;
+    const int base = x0 - HALO;
     const int X = base + lane;
     int xe, lm, lp;  // node column; LDS lanes of its x-1 / x+1 stencil neighbours
     if (D.open_x) {
@@ -428,93 +492,125 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
     }
     const int lanes_of[3] = {lm, lane, lp};
     const bool out_lane = lane >= HALO && lane < TILE_LANES - HALO && X < D.nx;
+    const bool gather_lane = lane >= 1 && lane < TILE_LANES - 1;
     const AT eps = AT(D.eps);
-    const int y0 = it.y0, y1 = it.y1;
-    const int r_first = y0 - HALO + 1 - R;  // first A row is y0 - 4
+    const int r_first = y0 - HALO + 1 - R;  // first stage A row is y0 - 4
 
-    // prefetched inputs of the next stage A row: pulled populations, class word, colour row + 1
-    T pf[9];
-    uint32_t pm = SELF_SOLID;
-    AT pc = AT(0), pvx = AT(0), pvy = AT(0);
+    const Rsrc f_in = make_rsrc(A.fin, A.f_set_bytes), f_out = make_rsrc(A.fout, A.f_set_bytes);
+    const Rsrc c_in = make_rsrc(A.cin, 3 * A.c_plane_bytes), c_out = make_rsrc(A.cout, 3 * A.c_plane_bytes);
+    const Rsrc r_mask = make_rsrc(A.mask, (uint32_t)A.plane * 2u);
+    const Rsrc r_ns = make_rsrc(A.nsx, 2 * A.ns_stride_bytes);
+    const uint32_t FP = A.f_plane_bytes, CP = A.c_plane_bytes;
 
     auto row_ok_a = [&](int y) { return y >= y0 - HALO + 1 && y < y1 + HALO - 1; };
     auto row_ok_c = [&](int y) { return y >= y0 - HALO && y < y1 + HALO; };
-    const uint32_t P = (uint32_t)A.plane;
-    auto prefetch = [&](int ya) {
-        pm = SELF_SOLID;
-        if (row_ok_a(ya)) {
-            const int yw = wrap(ya, D.ny);
-            const Nbr nb = make_nbr(D, xe, yw);
-            pm = Plane<uint16_t>(A.mask, P).load((uint32_t)(nb.row[1] + xe));
-#pragma unroll
-            for (int a = 0; a < 9; a++) {
-                const uint32_t src = (uint32_t)(A.own ? nb.row[1] + xe : pull_src(nb, a));
-                pf[a] = Plane<T>(A.fin + a * A.plane, P).load(src);
-            }
-        }
-        const int yc = ya + 1;
-        if (row_ok_c(yc)) {
-            const uint32_t nd = (uint32_t)D.off + (uint32_t)wrap(yc, D.ny) * (uint32_t)D.nx + xe;
-            pc = Plane<AT>(A.cin, P).load(nd);
-            pvx = Plane<AT>(A.vxin, P).load(nd);
-            pvy = Plane<AT>(A.vyin, P).load(nd);
-        }
+    auto node_of = [&](int y) {  // node index of (xe, y), y periodic
+        return (uint32_t)D.off + (uint32_t)wrap(y, D.ny) * (uint32_t)D.nx + (uint32_t)xe;
     };
-    auto put_colour = [&](int yc) {
-        const int sl = yc & (Q - 1);
+
+    // Prefetched inputs of one stage A row ya: pulled populations (pulls from solid nodes
+    // redirected to the node's own opposite population), its class word, the wall normal on
+    // outermost fluid nodes, and the colour state of row ya + 1.  qm carries the class word of
+    // the row, loaded by the previous prefetch.
+    T pf[9];
+    uint32_t pm = SELF_SOLID, qm = 0;
+    AT pc = AT(0), pvx = AT(0), pvy = AT(0), pwx = AT(0), pwy = AT(0);
+    auto load_colour = [&](int yc) {
+        const uint32_t vo = row_ok_c(yc) ? node_of(yc) * CB : NOWHERE;
+        pc = Buf<AT>::load(c_in, vo, 0);
+        pvx = Buf<AT>::load(c_in, vo, CP);
+        pvy = Buf<AT>::load(c_in, vo, 2 * CP);
+    };
+    auto load_mask = [&](int y) {
+        qm = Buf<uint16_t>::load(r_mask, row_ok_a(y) ? node_of(y) * 2u : NOWHERE, 0);
+    };
+    auto prefetch = [&](int ya) {
+        load_colour(ya + 1);
+        const bool ok = row_ok_a(ya);
+        const uint32_t m = ok ? qm : SELF_SOLID;
+        const bool act = gather_lane && !(m & SELF_SOLID);
+        Nbr nb = make_nbr(D, xe, wrap(ya, D.ny));
+        const uint32_t self = (uint32_t)nb.row[1] + (uint32_t)xe;
+        const uint32_t vw = act && (m & FLUID_BND) ? self * CB : NOWHERE;
+        pwx = Buf<AT>::load(r_ns, vw, 0);
+        pwy = Buf<AT>::load(r_ns, vw, A.ns_stride_bytes);
+        // snapshot state: every population is the node's own, none bounces
+        const uint32_t solid_nbrs = A.own ? 0u : m;
+        if (A.own) {
+            nb.row[0] = nb.row[2] = nb.row[1];
+            nb.col[0] = nb.col[2] = xe;
+            nb.lo = nb.hi = false;
+        }
+#pragma unroll
+        for (int a = 0; a < 9; a++) {
+            // Direction a and its opposite share the plane offset of the lower of the two;
+            // the per-lane offset adds two planes for the higher one (opposites are 2 apart).
+            const int lo = a < OPP[a] ? a : OPP[a];
+            const uint32_t up = a == lo ? 0u : 2u * FP;
+            uint32_t vo = (uint32_t)pull_src(nb, a) * SB + up;
+            if (a > 0 && !pull_outside(nb, a) && (solid_nbrs & (1u << (OPP[a] - 1))))
+                vo = self * SB + (2u * FP - up);
+            pf[a] = Buf<T>::load(f_in, act ? vo : NOWHERE, (uint32_t)lo * FP);
+        }
+        pm = m;
+        load_mask(ya + R);
+    };
+    // colour row yc and wall normals of row yc - 1 into the LDS rings
+    auto put_prefetched = [&](int yc) {
+        const int sl = yc & (Q - 1), sw = (yc - 1) & (Q - 1);
         s_c[sl][lane] = pc;
         s_vx[sl][lane] = pvx;
         s_vy[sl][lane] = pvy;
+        s_wx[sw][lane] = pwx;
+        s_wy[sw][lane] = pwy;
     };
-
-    // prologue: colour rows r_first + R - 1 .. r_first + 2R and the first A row's inputs
-    if (w < 2) {
-        const int yc = r_first + R - 1 + w;
-        if (row_ok_c(yc)) {
-            const uint32_t nd = (uint32_t)D.off + (uint32_t)wrap(yc, D.ny) * (uint32_t)D.nx + xe;
-            pc = Plane<AT>(A.cin, P).load(nd);
-            pvx = Plane<AT>(A.vxin, P).load(nd);
-            pvy = Plane<AT>(A.vyin, P).load(nd);
-        }
-        put_colour(yc);
-    }
-    prefetch(r_first + R + w);
-    put_colour(r_first + R + 1 + w);
-    __syncthreads();
 
     AT d[9], dn[9];
     AT rR = AT(0), rB = AT(0), rN = AT(0), rRn = AT(0), rBn = AT(0), rNn = AT(0);
 #pragma unroll
     for (int a = 0; a < 9; a++) d[a] = dn[a] = AT(0);
 
-    for (int r = r_first; r < y1; r += R) {
-        // ---- A: gather, densities, colour indicator
-        {
-            const int ya = r + R + w;
-            const int sl = ya & (Q - 1);
-            const uint32_t m = pm;
-            AT rn = AT(0);
-            if (lane >= 1 && lane < TILE_LANES - 1 && !(m & SELF_SOLID)) {
-                const int yw = wrap(ya, D.ny);
-                const Nbr nb = make_nbr(D, xe, yw);
+    // ---- A: gather, densities, colour indicator of row ya into LDS and dn / rRn / rBn / rNn
+    auto stage_a = [&](int ya) {
+        const int sl = ya & (Q - 1);
+        const uint32_t m = pm;
+        AT rn = AT(0);
+        if (gather_lane && !(m & SELF_SOLID)) {
+            const int yw = wrap(ya, D.ny);
+            const Nbr nb = make_nbr(D, xe, yw);
 #pragma unroll
-                for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(pf[a], a);
-                finish_gather(A, D, xe, yw, m, nb, true, dn, rRn, rBn,
-                              [&](int a, AT &c, AT &vx, AT &vy) {
-                                  const int s2 = (ya - EY[a]) & (Q - 1);
-                                  const int l2 = lanes_of[1 - EX[a]];
-                                  c = s_c[s2][l2];
-                                  vx = s_vx[s2][l2];
-                                  vy = s_vy[s2][l2];
-                              });
-                rn = colour_indicator(rRn, rBn);
-                rNn = rn;
-            }
-            s_m[sl][lane] = (uint16_t)m;
-            s_rn[sl][lane] = rn;
+            for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(pf[a], a);
+            finish_gather<true>(A, D, xe, yw, m, nb, true, dn, rRn, rBn,
+                                [&](int a, AT &c, AT &vx, AT &vy) {
+                                    const int s2 = (ya - EY[a]) & (Q - 1);
+                                    const int l2 = lanes_of[1 - EX[a]];
+                                    c = s_c[s2][l2];
+                                    vx = s_vx[s2][l2];
+                                    vy = s_vy[s2][l2];
+                                });
+            rn = colour_indicator(rRn, rBn);
+            rNn = rn;
         }
-        // inputs of the next iteration's stage A row, in flight during stages B-E
-        prefetch(r + 2 * R + w);
+        s_m[sl][lane] = (uint16_t)m;
+        s_rn[sl][lane] = rn;
+    };
+
+    // prologue: colour rows r_first + R - 1 .. r_first + 2R, stage A of rows r_first + R + w
+    load_mask(r_first + R + w);
+    if (w < 2) {
+        load_colour(r_first + R - 1 + w);
+        const int sl = (r_first + R - 1 + w) & (Q - 1);
+        s_c[sl][lane] = pc;
+        s_vx[sl][lane] = pvx;
+        s_vy[sl][lane] = pvy;
+    }
+    prefetch(r_first + R + w);
+    put_prefetched(r_first + R + 1 + w);
+    __syncthreads();
+    stage_a(r_first + R + w);
+    prefetch(r_first + 2 * R + w);
+
+    for (int r = r_first; r < y1; r += R) {
         __syncthreads();
         // ---- B: virtual colour indicator on outermost solid nodes (Eq. 29)
         {
@@ -555,10 +651,8 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                         gx = AT(3) * sx;
                         gy = AT(3) * sy;
                     }
-                    if (m & FLUID_BND) {
-                        const size_t nd = (size_t)D.off + (size_t)wrap(yc, D.ny) * D.nx + xe;
-                        wetting_correct(A.nsx[nd], A.nsy[nd], AT(D.cos_t), AT(D.sin_t), eps, gx, gy);
-                    }
+                    if (m & FLUID_BND)
+                        wetting_correct(s_wx[sl][lane], s_wy[sl][lane], AT(D.cos_t), AT(D.sin_t), eps, gx, gy);
                     const AT g = fsqrt(gx * gx + gy * gy);
                     if (g > eps) unit_normal(gx, gy, g, nx, ny);
                 }
@@ -592,14 +686,18 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                     s_ny[sl][lane] = numy * iden;
                 }
             }
-            // colour row for the next iteration's stage A (its loads were issued after A)
-            put_colour(r + 2 * R + 1 + w);
+            // colour row and wall normals for the coming stage A (loads issued last iteration)
+            put_prefetched(r + 2 * R + 1 + w);
         }
         __syncthreads();
         // ---- E: curvature (Eq. 13), force (Eq. 10), collision, recolouring state (Eq. 14)
         {
             const int ye = r + w;
             const int sl = ye & (Q - 1);
+            AT o[9], c = AT(0), bx = AT(0), by = AT(0);
+#pragma unroll
+            for (int a = 0; a < 9; a++) o[a] = AT(0);
+            uint32_t vf = NOWHERE, vc = NOWHERE;
             if (out_lane && ye >= y0 && ye < y1 && !(s_m[sl][lane] & SELF_SOLID)) {
                 AT dxnx = AT(0), dynx = AT(0), dxny = AT(0), dyny = AT(0);
                 {
@@ -627,31 +725,35 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                 const AT kappa = -nx * nx * dyny - ny * ny * dxnx + nx * ny * (dynx + dxny);
                 const AT Fx = AT(D.half_sigma) * kappa * gx;
                 const AT Fy = AT(D.half_sigma) * kappa * gy;
-                AT o[9], rho, ux, uy;
+                AT rho, ux, uy;
                 collide(D, d, Fx, Fy, rN, o, rho, ux, uy);
                 const AT rs = rR + rB;
-                const AT c = quotient(rR, rs);
+                c = quotient(rR, rs);
                 const AT b = AT(D.beta) * rB * c;
-                const uint32_t nd = (uint32_t)D.off + (uint32_t)wrap(ye, D.ny) * (uint32_t)D.nx + xe;
-#pragma unroll
-                for (int a = 0; a < 9; a++)
-                    Plane<T>(A.fout + a * A.plane, P).store(nd, Codec<T>::encode(o[a], a));
-                Plane<AT>(A.cout, P).store(nd, c);
-                Plane<AT>(A.vxout, P).store(nd, b * nx);
-                Plane<AT>(A.vyout, P).store(nd, b * ny);
+                bx = b * nx;
+                by = b * ny;
+                const uint32_t nd = node_of(ye);
+                vf = nd * SB;
+                vc = nd * CB;
                 if (!(isfinite(rho) && isfinite(ux) && isfinite(uy))) atomicOr(A.flag, 1);
             }
+#pragma unroll
+            for (int a = 0; a < 9; a++) Buf<T>::store(f_out, vf, (uint32_t)a * FP, Codec<T>::encode(o[a], a));
+            Buf<AT>::store(c_out, vc, 0, c);
+            Buf<AT>::store(c_out, vc, CP, bx);
+            Buf<AT>::store(c_out, vc, 2 * CP, by);
         }
 #pragma unroll
         for (int a = 0; a < 9; a++) d[a] = dn[a];
         rR = rRn;
         rB = rBn;
         rN = rNn;
-        // No barrier here.  The next stage A writes s_m / s_rn rows r + 2R .. r + 3R - 1, which
-        // alias rows r .. r + R - 1; of those, stage E reads only s_m of its own row, written
-        // by its own wavefront.  The colour ring rows written in stage D are read only by the
-        // next stage A (after the D-E barrier), and the n / g rings only change after the
-        // next A-B barrier.
+        // Stage A of the next iteration, without a barrier: it writes s_m / s_rn rows
+        // r + 2R .. r + 3R - 1, which alias rows r .. r + R - 1; of those, stage E reads only
+        // s_m of its own row, written by its own wavefront.  The colour rows it reads were
+        // written in stage D, before the last barrier.
+        stage_a(r + 2 * R + w);
+        prefetch(r + 3 * R + w);
     }
 }
 
@@ -660,7 +762,7 @@ template <class T>
 __global__ void read_kernel(const StepArgs<T, typename Codec<T>::AT> A, int dom, uint32_t which,
                             double *out) {
     using AT = typename Codec<T>::AT;
-    const DomDev &D = A.doms[dom];
+    DomC &D = *(DomC *)(A.doms + dom);
     const size_t nn = (size_t)D.nx * D.ny;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn;
          i += (size_t)gridDim.x * blockDim.x) {
@@ -678,7 +780,7 @@ __global__ void read_kernel(const StepArgs<T, typename Codec<T>::AT> A, int dom,
             for (int a = 0; a < 9; a++)
                 d[a] = Codec<T>::load(A.fin + a * A.plane + (A.own ? self : pull_src(nb, a)),
                                       a);
-            finish_gather(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
+            finish_gather<false>(A, D, x, y, m, nb, false, d, rR, rB, [&](int a, AT &c, AT &vx, AT &vy) {
                 const size_t src = (a == 0 || A.own) ? self : pull_src(nb, a);
                 c = A.cin[src];
                 vx = A.own ? AT(0) : A.vxin[src];
@@ -734,7 +836,7 @@ __global__ __launch_bounds__(MASS_THREADS) void mass_partial_kernel(
     using AT = typename Codec<T>::AT;
     const int dom = blockIdx.x / blocks_per_dom;
     const int b = blockIdx.x % blocks_per_dom;
-    const DomDev &D = A.doms[dom];
+    DomC &D = *(DomC *)(A.doms + dom);
     const size_t nn = (size_t)D.nx * D.ny;
     double sR = 0.0, sB = 0.0;
     for (size_t i = (size_t)b * MASS_THREADS + threadIdx.x; i < nn;
