@@ -230,7 +230,7 @@ struct lbm_ctx {
     std::vector<DomDev> doms;
     std::vector<WorkItem> items;
     int chunk_rows = 0;
-    int waves = 8;    // wavefronts (tile rows advanced per iteration) of the step kernel
+    int waves = 0;    // wavefronts (tile rows advanced per iteration) of the step kernel
     int parity = 0;   // buffer holding the current state
     int own = 1;      // current state is a node-local snapshot
     int64_t steps = 0;
@@ -284,30 +284,53 @@ AnyArgs make_args(const lbm_ctx *c, int parity) {
     return a;
 }
 
+// Work items, in the order the step kernel takes them.  The kernel deals blocks round-robin to
+// the 8 XCDs and gives XCD x the x-th of 8 equal consecutive runs of this list, so the order
+// decides which items share an L2 and run at the same time.  Within a domain the items are
+// band-major (all strips of a band of rows, then the next band): the blocks in flight then
+// stream a narrow band of every plane, which measured markedly faster than a strip at a time.
+// A domain with more items than one run is cut into strip groups of about one run each, so
+// that every XCD works through a compact region and neighbouring strips share its L2.
 std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk) {
+    size_t total = 0;
+    for (const auto &q : d) {
+        const int nch = std::max(1, (q.ny + chunk - 1) / chunk);
+        total += (size_t)strips_of(q) * nch;
+    }
+    const size_t run = std::max<size_t>(1, total / 8);
     std::vector<WorkItem> out;
+    out.reserve(total);
     for (int i = 0; i < (int)d.size(); i++) {
-        const int ny = d[i].ny;
+        const int ny = d[i].ny, S = strips_of(d[i]);
         const int nch = std::max(1, (ny + chunk - 1) / chunk);
         const int ch = ((ny + nch - 1) / nch + 3) / 4 * 4;
-        for (int s = 0; s < strips_of(d[i]); s++)
+        const size_t items = (size_t)S * nch;
+        const int groups = (int)std::min<size_t>(S, std::max<size_t>(1, (items + run / 2) / run));
+        for (int g = 0; g < groups; g++) {
+            const int s0 = (int)((long long)S * g / groups), s1 = (int)((long long)S * (g + 1) / groups);
             for (int k = 0; k < nch; k++) {
                 const int y0 = k * ch, y1 = std::min(ny, y0 + ch);
                 if (y0 >= y1) continue;
-                out.push_back(WorkItem{i, s * TILE_OUT, y0, y1});
+                for (int s = s0; s < s1; s++) out.push_back(WorkItem{i, s * TILE_OUT, y0, y1});
             }
+        }
     }
     return out;
 }
 
-// Tallest chunk that still yields enough work items to fill the chip (8 XCDs x 32 CUs, a few
-// resident blocks each); taller chunks repeat fewer halo rows.
+// Tallest chunk, up to 64 rows, that still yields 4096 work items.  Taller chunks repeat fewer
+// halo rows, but with the band-major order shorter bands measured faster on wide domains
+// (16384 x 512: 32 rows best), and enough items keep every CU busy on small ones.
 int auto_chunk(const std::vector<lbm_domain_desc> &d) {
-    const int cands[] = {128, 96, 64, 48, 32, 24, 16, 12, 8};
+    const int cands[] = {64, 48, 32, 24, 16, 12, 8};
     for (int ch : cands)
-        if (build_items(d, ch).size() >= 1024) return ch;
+        if (build_items(d, ch).size() >= 4096) return ch;
     return 8;
 }
+
+// Blocks of 4 tile rows (one wavefront per SIMD) measured at least as fast as blocks of 8 for
+// every storage type.
+int default_waves(int) { return 4; }
 
 int upload_items(lbm_ctx *c) {
     if (c->items.size() > c->L.items_cap) return fail(LBM_EINVAL, "work-item table overflow");
@@ -336,18 +359,26 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
         D.ny = q.ny;
         D.open_x = q.open_x ? 1 : 0;
         D.io_off = io;
-        D.inv2nu_r = 1.0 / (2.0 * q.nu_r);
-        D.inv2nu_b = 1.0 / (2.0 * q.nu_b);
-        D.half_sigma = 0.5 * q.sigma;
-        D.beta = q.beta;
-        D.cos_t = std::cos(th);
-        D.sin_t = std::sin(th);
-        D.s_e = q.s_e;
-        D.s_eps = q.s_eps;
-        D.s_q = q.s_q;
-        D.rho0 = q.rho0;
-        D.eps = q.eps;
-        D.outlet_u = q.outlet_u;
+        DomPar<double> &PD = D.d;
+        PD.inv2nu_r = 1.0 / (2.0 * q.nu_r);
+        PD.inv2nu_b = 1.0 / (2.0 * q.nu_b);
+        PD.half_sigma = 0.5 * q.sigma;
+        PD.beta = q.beta;
+        PD.cos_t = std::cos(th);
+        PD.sin_t = std::sin(th);
+        PD.s_e = q.s_e;
+        PD.s_eps = q.s_eps;
+        PD.s_q = q.s_q;
+        PD.ke = 6.0 * (1.0 - 0.5 * q.s_e);
+        PD.keps = 6.0 * (1.0 - 0.5 * q.s_eps);
+        PD.kq = 1.0 - 0.5 * q.s_q;
+        PD.rho0 = q.rho0;
+        PD.eps = q.eps;
+        PD.outlet_u = q.outlet_u;
+        PD.pad = 0.0;
+        const double *pd = &PD.rho0;
+        float *pf = &D.f.rho0;
+        for (size_t k = 0; k < sizeof(DomPar<double>) / sizeof(double); k++) pf[k] = (float)pd[k];
         for (int y = 0; y < q.ny; y++)
             for (int x = 0; x < q.nx; x++) {
                 const size_t k = (size_t)y * q.nx + x, g = off + k;
@@ -438,6 +469,7 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     c->desc.assign(domains, domains + n);
     c->doms.resize(n);
     c->chunk_rows = auto_chunk(c->desc);
+    c->waves = default_waves(storage);
     c->items = build_items(c->desc, c->chunk_rows);
     if (hipHostMalloc((void **)&c->mass_host, (2 * (size_t)n + 2) * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->flag_host, 64) != hipSuccess) {
@@ -526,7 +558,7 @@ int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves) {
     if (waves != 0 && waves != 4 && waves != 8) return fail(LBM_EINVAL, "waves must be 0, 4 or 8");
     HIP_OK(hipStreamSynchronize(c->stream));
     c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc);
-    c->waves = waves ? waves : 8;
+    c->waves = waves ? waves : default_waves(c->storage);
     c->items = build_items(c->desc, c->chunk_rows);
     return upload_items(c);
 }

@@ -19,14 +19,22 @@ constexpr int HALO = 5;            // halo columns per side: the step's dependen
                                    // walls is 4, plus one column for the colour-state stencil
 constexpr int TILE_OUT = TILE_LANES - 2 * HALO;  // output columns per tile
 
+// Per-domain parameters in one arithmetic type, with the constant factors of the collision
+// precomputed: ke = 6 (1 - s_e / 2), keps = 6 (1 - s_eps / 2), kq = 1 - s_q / 2 (the forcing
+// terms of Eq. 8 for e, epsilon and q).
+template <class AT>
+struct DomPar {
+    AT rho0, eps, inv2nu_r, inv2nu_b, half_sigma, beta, cos_t, sin_t;
+    AT s_e, s_eps, s_q, ke, keps, kq, outlet_u, pad;
+};
+
 struct DomDev {
     long long off;       // first node of the domain in every node plane
     int nx, ny;
     int open_x, pad0;
     long long io_off;    // first row of the domain in the inlet / outlet row arrays
-    double inv2nu_r, inv2nu_b;
-    double half_sigma, beta, cos_t, sin_t;
-    double s_e, s_eps, s_q, rho0, eps, outlet_u;
+    DomPar<double> d;    // parameters for FP64 arithmetic
+    DomPar<float> f;     // the same, rounded once, for FP32 arithmetic
 };
 
 // FP16 storage scale of direction a (the device codec uses the same constants).

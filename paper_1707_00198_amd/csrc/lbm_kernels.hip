@@ -111,7 +111,8 @@ struct Codec<__half> {
     // subnormal range without risking overflow.
     __device__ static constexpr float scale(int a) { return a == 0 ? 512.0f : (a < 5 ? 2048.0f : 8192.0f); }
     __device__ static float load(const __half *p, int a) { return __half2float(*p) * (1.0f / scale(a)); }
-    __device__ static float decode(__half v, int a) { return __half2float(v) * (1.0f / scale(a)); }
+    // one mixed-precision FMA (binary16 source, FP32 result); the product is exact
+    __device__ static float decode(__half v, int a) { return __builtin_fmaf(__half2float(v), 1.0f / scale(a), 0.0f); }
     __device__ static __half encode(float v, int a) { return __float2half_rn(v * scale(a)); }
 };
 
@@ -134,6 +135,11 @@ struct Plane {
 // so it becomes a scalar load, and a reload after vector stores never waits for the vector
 // loads in flight.
 using DomC = const __attribute__((address_space(4))) DomDev;
+template <class AT>
+using ParC = const __attribute__((address_space(4))) DomPar<AT>;
+// parameters of a domain in the arithmetic type AT
+__device__ __forceinline__ ParC<double> &par(DomC &D, double) { return D.d; }
+__device__ __forceinline__ ParC<float> &par(DomC &D, float) { return D.f; }
 
 __device__ __forceinline__ int wrap(int v, int n) {
     if ((unsigned)v < (unsigned)n) return v;
@@ -193,7 +199,8 @@ __device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, DomC &D,
                                               uint32_t m, const Nbr &nb, bool write_hist, AT d[9],
                                               AT &rR, AT &rB, ColourFn colour) {
     const size_t self = nb.row[1] + x;
-    const AT rho0 = AT(D.rho0);
+    ParC<AT> &P = par(D, AT());
+    const AT rho0 = P.rho0;
     AT cself, vxs, vys;
     colour(0, cself, vxs, vys);
     rR = AT(0);
@@ -249,7 +256,7 @@ __device__ __forceinline__ void finish_gather(const StepArgs<T, AT> &A, DomC &D,
         if (nb.hi) {
             // Convective outlet f_a <- [f_a(t) + U f_a(x - 1, t + 1)] / (1 + U), coloured with
             // this node's red fraction.
-            const AT U = AT(D.outlet_u);
+            const AT U = P.outlet_u;
             const uint32_t mm = A.mask[self - 1];
             const AT *h = A.hist_in + (D.io_off + y) * 3;
             const int unk[3] = {3, 6, 7};
@@ -335,7 +342,8 @@ __device__ __forceinline__ void wetting_correct(AT nsx, AT nsy, AT ct, AT st, AT
 template <class AT>
 __device__ __forceinline__ void collide(DomC &D, const AT d[9], AT Fx, AT Fy, AT rN,
                                         AT o[9], AT &rho_out, AT &ux_out, AT &uy_out) {
-    const AT rho0 = AT(D.rho0);
+    ParC<AT> &P = par(D, AT());
+    const AT rho0 = P.rho0;
     const AT drho = d[0] + d[1] + d[2] + d[3] + d[4] + d[5] + d[6] + d[7] + d[8];
     const AT sa = d[1] + d[2] + d[3] + d[4];
     const AT sd = d[5] + d[6] + d[7] + d[8];
@@ -353,20 +361,20 @@ __device__ __forceinline__ void collide(DomC &D, const AT d[9], AT Fx, AT Fy, AT
     const AT ux = (jx + AT(0.5) * Fx) * inv_rho;
     const AT uy = (jy + AT(0.5) * Fy) * inv_rho;
     // Eqs. 18 and 5: 1/nu interpolated in rho^N, tau = 3 nu + 1/2, s_nu = 1/tau
-    const AT inv_nu = (AT(1) + rN) * AT(D.inv2nu_r) + (AT(1) - rN) * AT(D.inv2nu_b);
+    const AT inv_nu = (AT(1) + rN) * P.inv2nu_r + (AT(1) - rN) * P.inv2nu_b;
     const AT sv = inv_nu * rcp(AT(3) + AT(0.5) * inv_nu);
-    const AT se = AT(D.s_e), seps = AT(D.s_eps), sq = AT(D.s_q);
+    const AT se = P.s_e, seps = P.s_eps, sq = P.s_q;
 
     const AT uu = ux * ux + uy * uy;
     const AT r3uu = AT(3) * rho * uu;
     const AT uF = ux * Fx + uy * Fy;
     const AT p0 = drho;
-    const AT p1 = m1 - se * (m1 + AT(2) * drho - r3uu) + (AT(1) - AT(0.5) * se) * (AT(6) * uF);
-    const AT p2 = m2 - seps * (m2 - drho + r3uu) - (AT(1) - AT(0.5) * seps) * (AT(6) * uF);
+    const AT p1 = m1 - se * (m1 + AT(2) * drho - r3uu) + P.ke * uF;
+    const AT p2 = m2 - seps * (m2 - drho + r3uu) - P.keps * uF;
     const AT p3 = rho * ux + AT(0.5) * Fx;
-    const AT p4 = m4 - sq * (m4 + rho * ux) - (AT(1) - AT(0.5) * sq) * Fx;
+    const AT p4 = m4 - sq * (m4 + rho * ux) - P.kq * Fx;
     const AT p5 = rho * uy + AT(0.5) * Fy;
-    const AT p6 = m6 - sq * (m6 + rho * uy) - (AT(1) - AT(0.5) * sq) * Fy;
+    const AT p6 = m6 - sq * (m6 + rho * uy) - P.kq * Fy;
     const AT p7 = m7 - sv * (m7 - rho * (ux * ux - uy * uy)) +
                   (AT(1) - AT(0.5) * sv) * (AT(2) * (ux * Fx - uy * Fy));
     const AT p8 = m8 - sv * (m8 - rho * ux * uy) + (AT(1) - AT(0.5) * sv) * (ux * Fy + uy * Fx);
@@ -476,24 +484,25 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
     const int x0 = __builtin_amdgcn_readfirstlane(itp->x0);
     const int y0 = __builtin_amdgcn_readfirstlane(itp->y0), y1 = __builtin_amdgcn_readfirstlane(itp->y1);
     DomC &D = *(DomC *)(A.doms + dom);
-    const int w = threadIdx.x / TILE_LANES;
+    // the wavefront index is uniform within a wavefront: row indices, row-range tests and LDS
+    // row slots then live in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / TILE_LANES);
     const int lane = threadIdx.x % TILE_LANES;
     const int base = x0 - HALO;
     const int X = base + lane;
-    int xe, lm, lp;  // node column; LDS lanes of its x-1 / x+1 stencil neighbours
-    if (D.open_x) {
-        xe = min(max(X, 0), D.nx - 1);
-        lm = max(xe - 1, 0) - base;
-        lp = min(xe + 1, D.nx - 1) - base;
-    } else {
-        xe = wrap(X, D.nx);
-        lm = lane - 1;
-        lp = lane + 1;
-    }
-    const int lanes_of[3] = {lm, lane, lp};
+    // Node column of the lane: periodic in x, or clamped to the edge columns of an open x axis.
+    // The x-1 / x+1 stencil neighbours are always the adjacent lanes.  At an open axis the
+    // stencil is clamped, so the lanes beyond an edge column stand for that edge node: after
+    // each stage that writes a stencil field they copy the edge lane's value (edge_lane >= 0),
+    // which only work items touching an open edge do.
+    const int xe = D.open_x ? min(max(X, 0), D.nx - 1) : wrap(X, D.nx);
+    const bool edge_item = D.open_x && (base < 0 || base + TILE_LANES > D.nx);
+    const int edge_lane = xe != X && D.open_x ? xe - base : -1;
+    const int lanes_of[3] = {lane - 1, lane, lane + 1};
     const bool out_lane = lane >= HALO && lane < TILE_LANES - HALO && X < D.nx;
     const bool gather_lane = lane >= 1 && lane < TILE_LANES - 1;
-    const AT eps = AT(D.eps);
+    ParC<AT> &P = par(D, AT());
+    const AT eps = P.eps;
     const int r_first = y0 - HALO + 1 - R;  // first stage A row is y0 - 4
 
     const Rsrc f_in = make_rsrc(A.fin, A.f_set_bytes), f_out = make_rsrc(A.fout, A.f_set_bytes);
@@ -509,9 +518,11 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
     };
 
     // Prefetched inputs of one stage A row ya: pulled populations (pulls from solid nodes
-    // redirected to the node's own opposite population), its class word, the wall normal on
-    // outermost fluid nodes, and the colour state of row ya + 1.  qm carries the class word of
-    // the row, loaded by the previous prefetch.
+    // redirected to the node's own opposite population), its class word and the wall normal on
+    // outermost fluid nodes; qm carries the class word of the row, loaded by the previous
+    // prefetch.  The colour state of row ya + 1 is loaded separately, in stage E before the
+    // stores: vector memory instructions complete in order, stores included, so the colour
+    // wait in the next stage D then never waits for stores issued just before it.
     T pf[9];
     uint32_t pm = SELF_SOLID, qm = 0;
     AT pc = AT(0), pvx = AT(0), pvy = AT(0), pwx = AT(0), pwy = AT(0);
@@ -525,7 +536,6 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         qm = Buf<uint16_t>::load(r_mask, row_ok_a(y) ? node_of(y) * 2u : NOWHERE, 0);
     };
     auto prefetch = [&](int ya) {
-        load_colour(ya + 1);
         const bool ok = row_ok_a(ya);
         const uint32_t m = ok ? qm : SELF_SOLID;
         const bool act = gather_lane && !(m & SELF_SOLID);
@@ -555,14 +565,24 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         pm = m;
         load_mask(ya + R);
     };
-    // colour row yc and wall normals of row yc - 1 into the LDS rings
-    auto put_prefetched = [&](int yc) {
-        const int sl = yc & (Q - 1), sw = (yc - 1) & (Q - 1);
+    // colour row yc into the LDS ring
+    auto put_colour = [&](int yc) {
+        const int sl = yc & (Q - 1);
         s_c[sl][lane] = pc;
         s_vx[sl][lane] = pvx;
         s_vy[sl][lane] = pvy;
-        s_wx[sw][lane] = pwx;
-        s_wy[sw][lane] = pwy;
+    };
+    // one row of outputs: populations, then the colour state (c, vx, vy)
+    auto store_row = [&](uint32_t vf, uint32_t vc, const AT (&o)[9], AT c, AT bx, AT by) {
+#pragma unroll
+        for (int a = 0; a < 9; a++) Buf<T>::store(f_out, vf, (uint32_t)a * FP, Codec<T>::encode(o[a], a));
+        Buf<AT>::store(c_out, vc, 0, c);
+        Buf<AT>::store(c_out, vc, CP, bx);
+        Buf<AT>::store(c_out, vc, 2 * CP, by);
+    };
+
+    auto replicate = [&](AT (*f)[TILE_LANES], int sl) {
+        if (edge_item && edge_lane >= 0) f[sl][lane] = f[sl][edge_lane];
     };
 
     AT d[9], dn[9];
@@ -593,6 +613,9 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         }
         s_m[sl][lane] = (uint16_t)m;
         s_rn[sl][lane] = rn;
+        s_wx[sl][lane] = pwx;
+        s_wy[sl][lane] = pwy;
+        replicate(s_rn, sl);
     };
 
     // prologue: colour rows r_first + R - 1 .. r_first + 2R, stage A of rows r_first + R + w
@@ -604,10 +627,15 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         s_vx[sl][lane] = pvx;
         s_vy[sl][lane] = pvy;
     }
+    load_colour(r_first + R + 1 + w);
     prefetch(r_first + R + w);
-    put_prefetched(r_first + R + 1 + w);
+    put_colour(r_first + R + 1 + w);
     __syncthreads();
     stage_a(r_first + R + w);
+    load_colour(r_first + 2 * R + 1 + w);
+    // as many (dropped) stores after the colour loads as the loop issues there, so that the
+    // wait in the first stage D is the same as in every later one
+    store_row(NOWHERE, NOWHERE, d, rR, rB, rN);
     prefetch(r_first + 2 * R + w);
 
     for (int r = r_first; r < y1; r += R) {
@@ -630,6 +658,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                     s_rn[sl][lane] = num * rcp(den);
                 }
             }
+            replicate(s_rn, sl);
         }
         __syncthreads();
         // ---- C: colour gradient (Eq. 28), wetting correction, interface normal (Eq. 22)
@@ -652,7 +681,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                         gy = AT(3) * sy;
                     }
                     if (m & FLUID_BND)
-                        wetting_correct(s_wx[sl][lane], s_wy[sl][lane], AT(D.cos_t), AT(D.sin_t), eps, gx, gy);
+                        wetting_correct(s_wx[sl][lane], s_wy[sl][lane], P.cos_t, P.sin_t, eps, gx, gy);
                     const AT g = fsqrt(gx * gx + gy * gy);
                     if (g > eps) unit_normal(gx, gy, g, nx, ny);
                 }
@@ -661,6 +690,8 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                 s_nx[sl][lane] = nx;
                 s_ny[sl][lane] = ny;
             }
+            replicate(s_nx, sl);
+            replicate(s_ny, sl);
         }
         __syncthreads();
         // ---- D: virtual interface normals on outermost solid nodes (Eq. 29, second BC)
@@ -686,17 +717,21 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                     s_ny[sl][lane] = numy * iden;
                 }
             }
-            // colour row and wall normals for the coming stage A (loads issued last iteration)
-            put_prefetched(r + 2 * R + 1 + w);
+            replicate(s_nx, sl);
+            replicate(s_ny, sl);
+            // colour row for the coming stage A (loads issued in the last stage E)
+            put_colour(r + 2 * R + 1 + w);
         }
         __syncthreads();
         // ---- E: curvature (Eq. 13), force (Eq. 10), collision, recolouring state (Eq. 14)
         {
             const int ye = r + w;
             const int sl = ye & (Q - 1);
-            AT o[9], c = AT(0), bx = AT(0), by = AT(0);
+            // Lanes without an output node store to NOWHERE, so their values are never written;
+            // they start from registers that die here, which costs no moves.
+            AT o[9], c = rR, bx = rB, by = rN;
 #pragma unroll
-            for (int a = 0; a < 9; a++) o[a] = AT(0);
+            for (int a = 0; a < 9; a++) o[a] = d[a];
             uint32_t vf = NOWHERE, vc = NOWHERE;
             if (out_lane && ye >= y0 && ye < y1 && !(s_m[sl][lane] & SELF_SOLID)) {
                 AT dxnx = AT(0), dynx = AT(0), dxny = AT(0), dyny = AT(0);
@@ -723,25 +758,22 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                 const AT nx = s_nx[sl][lane], ny = s_ny[sl][lane];
                 const AT gx = s_gx[sl][lane], gy = s_gy[sl][lane];
                 const AT kappa = -nx * nx * dyny - ny * ny * dxnx + nx * ny * (dynx + dxny);
-                const AT Fx = AT(D.half_sigma) * kappa * gx;
-                const AT Fy = AT(D.half_sigma) * kappa * gy;
+                const AT Fx = P.half_sigma * kappa * gx;
+                const AT Fy = P.half_sigma * kappa * gy;
                 AT rho, ux, uy;
                 collide(D, d, Fx, Fy, rN, o, rho, ux, uy);
                 const AT rs = rR + rB;
                 c = quotient(rR, rs);
-                const AT b = AT(D.beta) * rB * c;
+                const AT b = P.beta * rB * c;
                 bx = b * nx;
                 by = b * ny;
                 const uint32_t nd = node_of(ye);
                 vf = nd * SB;
                 vc = nd * CB;
-                if (!(isfinite(rho) && isfinite(ux) && isfinite(uy))) atomicOr(A.flag, 1);
+                if (!isfinite(rho + ux + uy)) atomicOr(A.flag, 1);  // any NaN or overflow
             }
-#pragma unroll
-            for (int a = 0; a < 9; a++) Buf<T>::store(f_out, vf, (uint32_t)a * FP, Codec<T>::encode(o[a], a));
-            Buf<AT>::store(c_out, vc, 0, c);
-            Buf<AT>::store(c_out, vc, CP, bx);
-            Buf<AT>::store(c_out, vc, 2 * CP, by);
+            load_colour(r + 3 * R + 1 + w);  // for the next stage D; see prefetch
+            store_row(vf, vc, o, c, bx, by);
         }
 #pragma unroll
         for (int a = 0; a < 9; a++) d[a] = dn[a];
@@ -807,7 +839,7 @@ __global__ void read_kernel(const StepArgs<T, typename Codec<T>::AT> A, int dom,
                     vsx = A.vxin[src];
                     vsy = A.vyin[src];
                 }
-                const double fa = wgt<double>(a) * D.rho0 + (double)d[a];
+                const double fa = wgt<double>(a) * D.d.rho0 + (double)d[a];
                 const double t = wgt<double>(a) * (EX[a] * (double)vsx + EY[a] * (double)vsy);
                 fR[a] = (double)cs * fa + t;
                 fB[a] = (1.0 - (double)cs) * fa - t;
