@@ -48,9 +48,17 @@ typedef enum {
 } lbm_status;
 
 /* Population storage.  Arithmetic is FP64 for LBM_STORE_F64 and FP32 otherwise.  Populations
- * are stored as deviations f_alpha - w_alpha * rho0; LBM_STORE_F16 stores them in binary16
- * multiplied by a power-of-two scale per direction.  Colour state is FP64 / FP32. */
-typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_storage;
+ * are stored as deviations f_alpha - w_alpha * rho0.  The 16-bit storages multiply them by a
+ * power-of-two scale per direction (2^9 rest, 2^11 axis, 2^13 diagonal): LBM_STORE_F16 stores
+ * binary16, LBM_STORE_C16 a format with one more significand bit (sign, 4-bit exponent with
+ * bias 7, 11-bit fraction, subnormals; relative rounding error below 2^-12, saturating beyond
+ * |deviation| = 2.25 w_alpha rho0).  Colour state is FP64 / FP32. */
+typedef enum {
+    LBM_STORE_F64 = 0,
+    LBM_STORE_F32 = 1,
+    LBM_STORE_F16 = 2,
+    LBM_STORE_C16 = 3
+} lbm_storage;
 
 /* One domain.  Host pointers are read during lbm_create only. */
 typedef struct {

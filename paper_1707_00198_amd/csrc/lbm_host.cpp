@@ -44,7 +44,7 @@ const double WH[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-size_t storage_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }
+size_t storage_bytes(int storage) { return storage == 0 ? 8 : (storage == 1 ? 4 : 2); }  // 2: f16, 3: c16
 size_t colour_bytes(int storage) { return storage == 0 ? 8 : 4; }
 
 // Byte offsets of every region, shared by query and create.
@@ -115,7 +115,7 @@ Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
 
 int validate(const lbm_domain_desc *d, int n, int storage) {
     if (!d || n <= 0) return fail(LBM_EINVAL, "need at least one domain");
-    if (storage < 0 || storage > 2) return fail(LBM_EINVAL, "unknown storage %d", storage);
+    if (storage < 0 || storage > 3) return fail(LBM_EINVAL, "unknown storage %d", storage);
     for (int i = 0; i < n; i++) {
         const lbm_domain_desc &q = d[i];
         if (q.nx < 1 || q.ny < 1) return fail(LBM_EINVAL, "domain %d: bad extent %dx%d", i, q.nx, q.ny);
@@ -218,6 +218,23 @@ template <>
 float encode<float>(double v, float) { return (float)v; }
 template <>
 __half encode<__half>(double v, float scale) { return __float2half_rn((float)(v * scale)); }
+// The 16-bit format of C16 from exact double arithmetic (round to nearest, ties to even).
+template <>
+C16 encode<C16>(double v, float scale) {
+    const double x = std::fabs(v * scale);
+    uint32_t r;
+    if (!(x >= 0x1p-6)) {
+        r = (uint32_t)std::nearbyint(x * 0x1p17);  // subnormal; 2048 is the smallest normal
+    } else {
+        int ex;
+        const double fr = std::frexp(x, &ex);  // x = fr 2^ex, fr in [0.5, 1)
+        const int e = std::min(ex - 1 + 7, 16);
+        // a rounding carry (fraction 2048) moves into the exponent
+        r = ((uint32_t)e << 11) + (uint32_t)std::nearbyint((2.0 * fr - 1.0) * 2048.0);
+    }
+    r = std::min<uint32_t>(r, 0x7FFFu);
+    return C16{(uint16_t)(r | (std::signbit(v) ? 0x8000u : 0u))};
+}
 
 }  // namespace
 
@@ -280,7 +297,8 @@ AnyArgs make_args(const lbm_ctx *c, int parity) {
     std::memset(&a, 0, sizeof a);
     if (c->storage == 0) fill_args(c, parity, *reinterpret_cast<StepArgs<double, double> *>(a.bytes));
     else if (c->storage == 1) fill_args(c, parity, *reinterpret_cast<StepArgs<float, float> *>(a.bytes));
-    else fill_args(c, parity, *reinterpret_cast<StepArgs<__half, float> *>(a.bytes));
+    else if (c->storage == 2) fill_args(c, parity, *reinterpret_cast<StepArgs<__half, float> *>(a.bytes));
+    else fill_args(c, parity, *reinterpret_cast<StepArgs<C16, float> *>(a.bytes));
     return a;
 }
 
@@ -391,7 +409,7 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
                 if (s) continue;
                 const double rr = q.rho_r0[k], rb = q.rho_b0[k], rho = rr + rb;
                 for (int a = 0; a < 9; a++)
-                    f[a * P + g] = encode<T>(WH[a] * (rho - q.rho0), c->storage == 2 ? fp16_scale(a) : 1.0f);
+                    f[a * P + g] = encode<T>(WH[a] * (rho - q.rho0), c->storage >= 2 ? fp16_scale(a) : 1.0f);
                 col[g] = (AT)(rr / rho);
                 if (q.open_x && x == q.nx - 1) {
                     hist[3 * (io + y) + 0] = (AT)(WH[3] * (rho - q.rho0));
@@ -478,7 +496,8 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     }
     if (storage == 0) rc = create_t<double, double>(c, domains);
     else if (storage == 1) rc = create_t<float, float>(c, domains);
-    else rc = create_t<__half, float>(c, domains);
+    else if (storage == 2) rc = create_t<__half, float>(c, domains);
+    else rc = create_t<C16, float>(c, domains);
     if (rc) {
         lbm_destroy(c);
         return rc;

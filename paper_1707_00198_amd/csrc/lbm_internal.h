@@ -40,6 +40,14 @@ struct DomDev {
 // FP16 storage scale of direction a (the device codec uses the same constants).
 inline float fp16_scale(int a) { return a == 0 ? 512.0f : (a < 5 ? 2048.0f : 8192.0f); }
 
+// 16-bit storage with one more significand bit than binary16: sign, 4-bit exponent (bias 7),
+// 11-bit fraction, subnormals at exponent 0.  A population deviation d of direction a is
+// stored as d * fp16_scale(a), so that the format covers |d| < 2.25 w_a rho0 (larger values
+// saturate) with a relative rounding error below 2^-12.
+struct C16 {
+    uint16_t bits;
+};
+
 struct WorkItem {
     int dom, x0, y0, y1;
 };
@@ -70,7 +78,7 @@ struct StepArgs {
     uint32_t f_plane_bytes, f_set_bytes, c_plane_bytes, ns_stride_bytes;
 };
 
-// Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16.
+// Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16, 3 c16.
 hipError_t launch_step(int storage, const void *args, int n_items, int waves, hipStream_t s);
 hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, uint32_t which,
                        double *out, hipStream_t s);

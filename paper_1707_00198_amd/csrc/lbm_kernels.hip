@@ -116,6 +116,37 @@ struct Codec<__half> {
     __device__ static __half encode(float v, int a) { return __float2half_rn(v * scale(a)); }
 };
 
+template <>
+struct Codec<C16> {
+    using AT = float;
+    // The 15 exponent-and-fraction bits, moved to bit 12 of an FP32 word, read as an FP32
+    // number 2^(e - 127) (1 + f / 2^11) (or its subnormal for e = 0); one multiplication by
+    // 2^(127 - 7) / scale(a) then gives the deviation.  FP32 subnormals are kept (the kernels
+    // run with denormals enabled), so the small values decode exactly.
+    __device__ static constexpr float dec(int a) {
+        return a == 0 ? 0x1p111f : (a < 5 ? 0x1p109f : 0x1p107f);
+    }
+    __device__ static constexpr float enc(int a) {
+        return a == 0 ? 0x1p-111f : (a < 5 ? 0x1p-109f : 0x1p-107f);
+    }
+    __device__ static float decode(C16 v, int a) {
+        const uint32_t u = v.bits;
+        return __uint_as_float(((u & 0x7FFFu) << 12) | ((u & 0x8000u) << 16)) * dec(a);
+    }
+    __device__ static float load(const C16 *p, int a) { return decode(*p, a); }
+    // The inverse map: the same FP32 word, rounded to 11 fraction bits (to nearest, ties to
+    // even; a carry moves into the exponent), saturating at the largest finite value.  Below
+    // the smallest normal the scaling product is an FP32 subnormal, rounded first on a grid
+    // 2^12 times finer: within 2^-12 of a halfway point that result can differ by one unit
+    // from a single rounding.
+    __device__ static C16 encode(float v, int a) {
+        const uint32_t b = __float_as_uint(v * enc(a));
+        const uint32_t mag = b & 0x7FFFFFFFu;
+        const uint32_t r = min((mag + 0x7FFu + ((mag >> 12) & 1u)) >> 12, 0x7FFFu);
+        return C16{(uint16_t)(r | ((b >> 16) & 0x8000u))};
+    }
+};
+
 // Periodic wrap of an index that is usually already in [0, n): one compare on the fast path.
 // Element access into one node plane: a uniform base pointer plus a 32-bit byte offset, so
 // that each access needs one vector offset (planes are below 2^31 bytes, checked on the host).
@@ -451,6 +482,15 @@ struct Buf<__half> {
     }
     __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, __half v) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, vo, so, 0);
+    }
+};
+template <>
+struct Buf<C16> {
+    __device__ static C16 load(Rsrc r, uint32_t vo, uint32_t so) {
+        return C16{__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)};
+    }
+    __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, C16 v) {
+        __builtin_amdgcn_raw_buffer_store_b16(v.bits, r, vo, so, 0);
     }
 };
 template <>
@@ -927,6 +967,7 @@ hipError_t launch_step(int storage, const void *args, int n_items, int waves, hi
         case 0: return step_t<double>(args, n_items, waves, s);
         case 1: return step_t<float>(args, n_items, waves, s);
         case 2: return step_t<__half>(args, n_items, waves, s);
+        case 3: return step_t<C16>(args, n_items, waves, s);
     }
     return hipErrorInvalidValue;
 }
@@ -947,6 +988,7 @@ hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, u
         case 0: return read_t<double>(args, dom, nx, ny, which, out, s);
         case 1: return read_t<float>(args, dom, nx, ny, which, out, s);
         case 2: return read_t<__half>(args, dom, nx, ny, which, out, s);
+        case 3: return read_t<C16>(args, dom, nx, ny, which, out, s);
     }
     return hipErrorInvalidValue;
 }
@@ -968,6 +1010,7 @@ hipError_t launch_mass(int storage, const void *args, int n_doms, const int *, d
         case 0: return mass_t<double>(args, n_doms, partials, bpd, out, s);
         case 1: return mass_t<float>(args, n_doms, partials, bpd, out, s);
         case 2: return mass_t<__half>(args, n_doms, partials, bpd, out, s);
+        case 3: return mass_t<C16>(args, n_doms, partials, bpd, out, s);
     }
     return hipErrorInvalidValue;
 }

@@ -16,7 +16,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbmcg.so")
 
-STORAGE = {"f64": 0, "f32": 1, "f16": 2}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "c16": 3}
 FIELD_RHO_R, FIELD_RHO_B, FIELD_POPS = 1, 2, 4
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
@@ -97,7 +97,7 @@ class Lattice:
     """A batch of domains advanced together by the fused HIP step.
 
     ``setups`` are objects with the attributes of ``workloads.Setup`` (solid, rho_r0, rho_b0,
-    params, open_x, inlet_ux, ns).  ``storage`` is 'f64', 'f32' or 'f16'.
+    params, open_x, inlet_ux, ns).  ``storage`` is 'f64', 'f32', 'f16' or 'c16'.
     """
 
     def __init__(self, setups: Sequence, storage: str = "f64", device="cuda:0"):
