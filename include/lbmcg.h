@@ -112,10 +112,15 @@ int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 #define LBM_FIELD_RHO_B 2u   /* blue density (one plane) */
 #define LBM_FIELD_POPS 4u    /* post-streaming populations f_{alpha,k}: 18 planes, colour-major
                                 (red alpha 0..8, then blue alpha 0..8) */
+#define LBM_FIELD_UX 8u      /* velocity u_x of Eq. 17 (with the half-force term) that the next
+                                collision uses (one plane; needs lbm_diag_attach) */
+#define LBM_FIELD_UY 16u     /* velocity u_y, likewise */
 
 /* Decode domain `domain`'s current state to FP64 into `out_dev` (device pointer, capacity
  * `out_count` doubles): one nx*ny plane per selected quantity, in bit order; solid nodes
- * read 0.  Enqueued on the context's stream.  LBM_ENOMEM if out_count is too small. */
+ * read 0.  Enqueued on the context's stream.  LBM_ENOMEM if out_count is too small.  The
+ * velocity planes are computed by a diagnostic launch of the step (no state is changed) and
+ * need an attached diagnostics buffer (LBM_ESTATE otherwise). */
 int lbm_read_fields(lbm_ctx *ctx, int domain, uint32_t which, double *out_dev,
                     size_t out_count);
 
@@ -138,6 +143,33 @@ int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves);
 size_t lbm_state_size(const lbm_ctx *ctx);
 int lbm_save_state(lbm_ctx *ctx, void *dst_dev);
 int lbm_load_state(lbm_ctx *ctx, const void *src_dev);
+
+/* Diagnostics of Sec. III (Eqs. 45-47), computed on the device from the current state.
+ * They need a caller-owned device buffer of lbm_diag_bytes bytes (256-byte aligned), handed
+ * over with lbm_diag_attach (NULL detaches); the library borrows it until it is detached or the
+ * context destroyed.  Each call synchronises the context's stream. */
+size_t lbm_diag_bytes(const lbm_ctx *ctx);
+int lbm_diag_attach(lbm_ctx *ctx, void *diag_dev, size_t bytes);
+
+/* Velocity statistics of every domain, without advancing the state: out_host[2*d] = |u|max
+ * (Eq. 46) over the fluid nodes of domain d, with u of Eq. 17 including the half-force term;
+ * out_host[2*d + 1] = max over fluid nodes of max(|u_x - u_x^s|, |u_y - u_y^s|) against the
+ * snapshot u^s (Eq. 45 when the snapshot was taken 500 steps earlier), NaN if no snapshot has
+ * been taken since lbm_diag_attach.  If `snapshot` is nonzero the current velocity becomes the
+ * snapshot afterwards.  LBM_ENONFINITE as lbm_mass. */
+int lbm_diag_velocity(lbm_ctx *ctx, int snapshot, double *out_host);
+
+/* FP64 colour masses of domain `domain` split by a region (the sums of Eq. 47): region_dev is a
+ * device array of nx*ny bytes (nonzero = inside); out_host[0..3] = sum of rho_R inside, rho_R
+ * outside, rho_B inside, rho_B outside, over fluid nodes. */
+int lbm_diag_region_mass(lbm_ctx *ctx, int domain, const uint8_t *region_dev, double *out_host);
+
+/* Interface positions along rows (contact line and finger tip of Sec. III): for each of the
+ * n_rows (1..4096) rows in rows_host, the first x, scanning from x = 0, with rho^N(x) > 0 >=
+ * rho^N(x + 1), interpolated linearly to x + rho^N(x) / (rho^N(x) - rho^N(x + 1)); NaN if the
+ * row has none.  rho^N of Eq. 12 from the current densities, 0 on solid nodes. */
+int lbm_diag_crossings(lbm_ctx *ctx, int domain, const int32_t *rows_host, int n_rows,
+                       double *out_host);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbm_last_error(void);

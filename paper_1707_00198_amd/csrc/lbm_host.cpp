@@ -253,6 +253,11 @@ struct lbm_ctx {
     int64_t steps = 0;
     double *mass_host = nullptr;
     int *flag_host = nullptr;
+    // diagnostics: caller's device buffer (lbm_diag_attach), pinned staging, snapshot state
+    char *diag = nullptr;
+    double *diag_host = nullptr;
+    int *rows_host = nullptr;
+    bool snap_valid = false;
 };
 
 namespace {
@@ -292,6 +297,37 @@ struct AnyArgs {
     alignas(16) unsigned char bytes[sizeof(StepArgs<double, double>)];
 };
 
+// Layout of the diagnostics buffer: velocity (u_x, u_y planes at the colour-plane stride), its
+// snapshot, reduction partials and results, and the row list and results of crossings.
+struct DiagLayout {
+    size_t u = 0, snap = 0, part = 0, res = 0, rows = 0, cross = 0, bytes = 0;
+};
+DiagLayout diag_layout(const lbm_ctx *c) {
+    DiagLayout D;
+    const size_t cp = c->L.vx_off - c->L.c_off;
+    size_t o = 0;
+    D.u = o;
+    o += 2 * cp;
+    D.snap = o;
+    o += 2 * cp;
+    D.part = o;
+    o += align_up(std::max<size_t>((size_t)c->n * DIAG_BLOCKS * 2, DIAG_BLOCKS * 4) * sizeof(double), 256);
+    D.res = o;
+    o += align_up(std::max<size_t>(2 * (size_t)c->n, 4) * sizeof(double), 256);
+    D.rows = o;
+    o += align_up(DIAG_MAX_ROWS * sizeof(int), 256);
+    D.cross = o;
+    o += align_up(DIAG_MAX_ROWS * sizeof(double), 256);
+    D.bytes = o;
+    return D;
+}
+
+template <class T, class AT>
+void set_diag_t(StepArgs<T, AT> &A, void *u) {
+    A.u_out = static_cast<AT *>(u);
+    A.diag = 1;
+}
+
 AnyArgs make_args(const lbm_ctx *c, int parity) {
     AnyArgs a;
     std::memset(&a, 0, sizeof a);
@@ -299,6 +335,17 @@ AnyArgs make_args(const lbm_ctx *c, int parity) {
     else if (c->storage == 1) fill_args(c, parity, *reinterpret_cast<StepArgs<float, float> *>(a.bytes));
     else if (c->storage == 2) fill_args(c, parity, *reinterpret_cast<StepArgs<__half, float> *>(a.bytes));
     else fill_args(c, parity, *reinterpret_cast<StepArgs<C16, float> *>(a.bytes));
+    return a;
+}
+
+// Arguments of a diagnostic launch on the current state: velocity into the diagnostics buffer.
+AnyArgs make_diag_args(const lbm_ctx *c) {
+    AnyArgs a = make_args(c, c->parity);
+    void *u = c->diag + diag_layout(c).u;
+    if (c->storage == 0) set_diag_t(*reinterpret_cast<StepArgs<double, double> *>(a.bytes), u);
+    else if (c->storage == 1) set_diag_t(*reinterpret_cast<StepArgs<float, float> *>(a.bytes), u);
+    else if (c->storage == 2) set_diag_t(*reinterpret_cast<StepArgs<__half, float> *>(a.bytes), u);
+    else set_diag_t(*reinterpret_cast<StepArgs<C16, float> *>(a.bytes), u);
     return a;
 }
 
@@ -541,14 +588,30 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
 int lbm_read_fields(lbm_ctx *c, int domain, uint32_t which, double *out_dev, size_t out_count) {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (domain < 0 || domain >= c->n) return fail(LBM_EINVAL, "domain %d out of range", domain);
-    if (which == 0 || (which & ~7u)) return fail(LBM_EINVAL, "bad field selection %u", which);
+    if (which == 0 || (which & ~31u)) return fail(LBM_EINVAL, "bad field selection %u", which);
     if (!out_dev) return fail(LBM_EINVAL, "output is NULL");
+    if ((which & 24u) && !c->diag)
+        return fail(LBM_ESTATE, "velocity fields need a diagnostics buffer (lbm_diag_attach)");
     const lbm_domain_desc &q = c->desc[domain];
-    const size_t planes = ((which & 1u) ? 1 : 0) + ((which & 2u) ? 1 : 0) + ((which & 4u) ? 18 : 0);
-    if (out_count < planes * (size_t)q.nx * q.ny)
-        return fail(LBM_ENOMEM, "output holds %zu doubles, need %zu", out_count, planes * (size_t)q.nx * q.ny);
+    const size_t nn = (size_t)q.nx * q.ny;
+    const size_t planes = ((which & 1u) ? 1 : 0) + ((which & 2u) ? 1 : 0) + ((which & 4u) ? 18 : 0) +
+                          ((which & 8u) ? 1 : 0) + ((which & 16u) ? 1 : 0);
+    if (out_count < planes * nn)
+        return fail(LBM_ENOMEM, "output holds %zu doubles, need %zu", out_count, planes * nn);
     AnyArgs a = make_args(c, c->parity);
-    HIP_OK(launch_read(c->storage, a.bytes, domain, q.nx, q.ny, which, out_dev, c->stream));
+    size_t p = 0;
+    if (which & 7u) {
+        HIP_OK(launch_read(c->storage, a.bytes, domain, q.nx, q.ny, which & 7u, out_dev, c->stream));
+        p = planes - ((which & 8u) ? 1 : 0) - ((which & 16u) ? 1 : 0);
+    }
+    if (which & 24u) {
+        AnyArgs da = make_diag_args(c);
+        HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->stream));
+        double *ox = (which & 8u) ? out_dev + (p++) * nn : nullptr;
+        double *oy = (which & 16u) ? out_dev + p * nn : nullptr;
+        HIP_OK(launch_velocity_copy(c->storage, a.bytes, domain, c->diag + diag_layout(c).u, ox, oy,
+                                    c->stream));
+    }
     return LBM_OK;
 }
 
@@ -612,11 +675,96 @@ int lbm_load_state(lbm_ctx *c, const void *src_dev) {
 
 const char *lbm_last_error(void) { return g_err.c_str(); }
 
+size_t lbm_diag_bytes(const lbm_ctx *c) { return c ? diag_layout(c).bytes : 0; }
+
+int lbm_diag_attach(lbm_ctx *c, void *diag_dev, size_t bytes) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->snap_valid = false;
+    if (!diag_dev) {
+        c->diag = nullptr;
+        return LBM_OK;
+    }
+    if (bytes < diag_layout(c).bytes)
+        return fail(LBM_ENOMEM, "diagnostics buffer holds %zu bytes, need %zu", bytes, diag_layout(c).bytes);
+    if ((uintptr_t)diag_dev & 255) return fail(LBM_EINVAL, "diagnostics buffer must be 256-byte aligned");
+    if (!c->diag_host) {
+        const size_t nd = std::max<size_t>(std::max<size_t>(2 * (size_t)c->n, 4), DIAG_MAX_ROWS);
+        if (hipHostMalloc((void **)&c->diag_host, nd * sizeof(double)) != hipSuccess ||
+            hipHostMalloc((void **)&c->rows_host, DIAG_MAX_ROWS * sizeof(int)) != hipSuccess)
+            return fail(LBM_EDEVICE, "pinned host allocation failed");
+    }
+    c->diag = static_cast<char *>(diag_dev);
+    return LBM_OK;
+}
+
+int lbm_diag_velocity(lbm_ctx *c, int snapshot, double *out_host) {
+    if (!c || !out_host) return fail(LBM_EINVAL, "null argument");
+    if (!c->diag) return fail(LBM_ESTATE, "no diagnostics buffer attached (lbm_diag_attach)");
+    const DiagLayout DL = diag_layout(c);
+    AnyArgs da = make_diag_args(c);
+    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->stream));
+    double *res = reinterpret_cast<double *>(c->diag + DL.res);
+    HIP_OK(launch_velocity_stats(c->storage, da.bytes, c->n, c->diag + DL.u,
+                                 c->snap_valid ? c->diag + DL.snap : nullptr,
+                                 reinterpret_cast<double *>(c->diag + DL.part), res, c->stream));
+    if (snapshot)
+        HIP_OK(hipMemcpyAsync(c->diag + DL.snap, c->diag + DL.u, DL.snap - DL.u, hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_OK(hipMemcpyAsync(c->diag_host, res, 2 * (size_t)c->n * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipMemcpyAsync(c->flag_host, c->scratch + c->L.flag, sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    std::memcpy(out_host, c->diag_host, 2 * (size_t)c->n * sizeof(double));
+    if (snapshot) c->snap_valid = true;
+    if (*c->flag_host) return fail(LBM_ENONFINITE, "a non-finite density or velocity appeared");
+    return LBM_OK;
+}
+
+int lbm_diag_region_mass(lbm_ctx *c, int domain, const uint8_t *region_dev, double *out_host) {
+    if (!c || !region_dev || !out_host) return fail(LBM_EINVAL, "null argument");
+    if (domain < 0 || domain >= c->n) return fail(LBM_EINVAL, "domain %d out of range", domain);
+    if (!c->diag) return fail(LBM_ESTATE, "no diagnostics buffer attached (lbm_diag_attach)");
+    const DiagLayout DL = diag_layout(c);
+    AnyArgs a = make_args(c, c->parity);
+    double *res = reinterpret_cast<double *>(c->diag + DL.res);
+    HIP_OK(launch_region_mass(c->storage, a.bytes, domain, region_dev,
+                              reinterpret_cast<double *>(c->diag + DL.part), res, c->stream));
+    HIP_OK(hipMemcpyAsync(c->diag_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    std::memcpy(out_host, c->diag_host, 4 * sizeof(double));
+    return LBM_OK;
+}
+
+int lbm_diag_crossings(lbm_ctx *c, int domain, const int32_t *rows_host, int n_rows, double *out_host) {
+    if (!c || !rows_host || !out_host) return fail(LBM_EINVAL, "null argument");
+    if (domain < 0 || domain >= c->n) return fail(LBM_EINVAL, "domain %d out of range", domain);
+    if (n_rows < 1 || n_rows > DIAG_MAX_ROWS) return fail(LBM_EINVAL, "row count %d outside [1, %d]", n_rows, DIAG_MAX_ROWS);
+    if (!c->diag) return fail(LBM_ESTATE, "no diagnostics buffer attached (lbm_diag_attach)");
+    for (int k = 0; k < n_rows; k++)
+        if (rows_host[k] < 0 || rows_host[k] >= c->desc[domain].ny)
+            return fail(LBM_EINVAL, "row %d outside the domain", rows_host[k]);
+    const DiagLayout DL = diag_layout(c);
+    std::memcpy(c->rows_host, rows_host, (size_t)n_rows * sizeof(int));
+    int *rows = reinterpret_cast<int *>(c->diag + DL.rows);
+    double *out = reinterpret_cast<double *>(c->diag + DL.cross);
+    HIP_OK(hipMemcpyAsync(rows, c->rows_host, (size_t)n_rows * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    AnyArgs a = make_args(c, c->parity);
+    HIP_OK(launch_crossings(c->storage, a.bytes, domain, rows, n_rows, out, c->stream));
+    HIP_OK(hipMemcpyAsync(c->diag_host, out, (size_t)n_rows * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    std::memcpy(out_host, c->diag_host, (size_t)n_rows * sizeof(double));
+    return LBM_OK;
+}
+
 void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     if (c->mass_host) (void)hipHostFree(c->mass_host);
     if (c->flag_host) (void)hipHostFree(c->flag_host);
+    if (c->diag_host) (void)hipHostFree(c->diag_host);
+    if (c->rows_host) (void)hipHostFree(c->rows_host);
     delete c;
 }
 

@@ -76,6 +76,12 @@ struct StepArgs {
     // host): one population plane, the 9 population planes, one colour-state plane (c, vx and
     // vy planes follow each other at this stride), and the offset of nsy after nsx.
     uint32_t f_plane_bytes, f_set_bytes, c_plane_bytes, ns_stride_bytes;
+    // Diagnostic launch (diag != 0): the state is read as in a step but nothing is written
+    // back (no populations, colour state or outlet history); instead the velocity of Eq. 17
+    // (with the half-force term) of every fluid node goes to u_out, u_x then u_y, planes
+    // c_plane_bytes apart.
+    AT *u_out;
+    int diag;
 };
 
 // Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16, 3 c16.
@@ -84,5 +90,21 @@ hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, u
                        double *out, hipStream_t s);
 hipError_t launch_mass(int storage, const void *args, int n_doms, const int *dom_nodes_begin,
                        double *partials, int n_blocks_per_dom, double *out, hipStream_t s);
+
+// Diagnostics (lbm_kernels.hip).
+constexpr int DIAG_BLOCKS = 64;     // blocks per domain of the diagnostic reductions
+constexpr int DIAG_MAX_ROWS = 4096;  // rows per lbm_diag_crossings call
+// Per domain: |u|max over fluid nodes, and max(|u_x - s_x|, |u_y - s_y|) against the snapshot.
+hipError_t launch_velocity_stats(int storage, const void *args, int n_doms, const void *u,
+                                 const void *snap, double *partials, double *out, hipStream_t s);
+// u_x, u_y of one domain as FP64 planes (solid nodes 0); either output may be NULL.
+hipError_t launch_velocity_copy(int storage, const void *args, int dom, const void *u,
+                                double *ox, double *oy, hipStream_t s);
+// FP64 {sum rho_R, sum rho_B} over fluid nodes with region != 0, then region == 0.
+hipError_t launch_region_mass(int storage, const void *args, int dom, const uint8_t *region,
+                              double *partials, double *out, hipStream_t s);
+// First x of each listed row where rho^N goes from > 0 to <= 0 (interpolated), NaN if none.
+hipError_t launch_crossings(int storage, const void *args, int dom, const int *rows, int n_rows,
+                            double *out, hipStream_t s);
 
 }  // namespace lbmcg

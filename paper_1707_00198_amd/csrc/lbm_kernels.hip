@@ -545,8 +545,10 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
     const AT eps = P.eps;
     const int r_first = y0 - HALO + 1 - R;  // first stage A row is y0 - 4
 
-    const Rsrc f_in = make_rsrc(A.fin, A.f_set_bytes), f_out = make_rsrc(A.fout, A.f_set_bytes);
-    const Rsrc c_in = make_rsrc(A.cin, 3 * A.c_plane_bytes), c_out = make_rsrc(A.cout, 3 * A.c_plane_bytes);
+    // a diagnostic launch writes no state (zero extents drop every store) but the velocity
+    const Rsrc f_in = make_rsrc(A.fin, A.f_set_bytes), f_out = make_rsrc(A.fout, A.diag ? 0u : A.f_set_bytes);
+    const Rsrc c_in = make_rsrc(A.cin, 3 * A.c_plane_bytes), c_out = make_rsrc(A.cout, A.diag ? 0u : 3 * A.c_plane_bytes);
+    const Rsrc u_out = make_rsrc(A.u_out, A.diag ? 2 * A.c_plane_bytes : 0u);
     const Rsrc r_mask = make_rsrc(A.mask, (uint32_t)A.plane * 2u);
     const Rsrc r_ns = make_rsrc(A.nsx, 2 * A.ns_stride_bytes);
     const uint32_t FP = A.f_plane_bytes, CP = A.c_plane_bytes;
@@ -640,7 +642,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
             const Nbr nb = make_nbr(D, xe, yw);
 #pragma unroll
             for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(pf[a], a);
-            finish_gather<true>(A, D, xe, yw, m, nb, true, dn, rRn, rBn,
+            finish_gather<true>(A, D, xe, yw, m, nb, !A.diag, dn, rRn, rBn,
                                 [&](int a, AT &c, AT &vx, AT &vy) {
                                     const int s2 = (ya - EY[a]) & (Q - 1);
                                     const int l2 = lanes_of[1 - EX[a]];
@@ -769,7 +771,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
             const int sl = ye & (Q - 1);
             // Lanes without an output node store to NOWHERE, so their values are never written;
             // they start from registers that die here, which costs no moves.
-            AT o[9], c = rR, bx = rB, by = rN;
+            AT o[9], c = rR, bx = rB, by = rN, ux = rR, uy = rB;
 #pragma unroll
             for (int a = 0; a < 9; a++) o[a] = d[a];
             uint32_t vf = NOWHERE, vc = NOWHERE;
@@ -800,7 +802,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
                 const AT kappa = -nx * nx * dyny - ny * ny * dxnx + nx * ny * (dynx + dxny);
                 const AT Fx = P.half_sigma * kappa * gx;
                 const AT Fy = P.half_sigma * kappa * gy;
-                AT rho, ux, uy;
+                AT rho;
                 collide(D, d, Fx, Fy, rN, o, rho, ux, uy);
                 const AT rs = rR + rB;
                 c = quotient(rR, rs);
@@ -814,6 +816,10 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
             }
             load_colour(r + 3 * R + 1 + w);  // for the next stage D; see prefetch
             store_row(vf, vc, o, c, bx, by);
+            if (A.diag) {
+                Buf<AT>::store(u_out, vc, 0, ux);
+                Buf<AT>::store(u_out, vc, CP, uy);
+            }
         }
 #pragma unroll
         for (int a = 0; a < 9; a++) d[a] = dn[a];
@@ -950,6 +956,155 @@ __global__ void mass_final_kernel(const double *partials, int n_doms, int blocks
     out[2 * dom + 1] = sB;
 }
 
+// ---------------------------------------------------------------- diagnostics (Sec. III)
+// Max-reductions and sums in FP64 over the fluid nodes of a domain; DIAG_BLOCKS blocks per
+// domain write partial results that a second kernel combines in a fixed order.
+constexpr int DIAG_THREADS = 256;
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = DIAG_THREADS / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + k]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = DIAG_THREADS / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// |u|max (Eq. 46) and the largest change of a velocity component against a snapshot (Eq. 45)
+template <class AT>
+__global__ __launch_bounds__(DIAG_THREADS) void velocity_stats_kernel(
+    const DomDev *doms, const uint16_t *mask, const AT *ux, const AT *uy, const AT *sx,
+    const AT *sy, double *partials) {
+    const int dom = blockIdx.x / DIAG_BLOCKS, b = blockIdx.x % DIAG_BLOCKS;
+    const DomDev &D = doms[dom];
+    const size_t nn = (size_t)D.nx * D.ny;
+    double umax = 0.0, e1 = 0.0;
+    for (size_t i = (size_t)b * DIAG_THREADS + threadIdx.x; i < nn; i += (size_t)DIAG_BLOCKS * DIAG_THREADS) {
+        const size_t g = D.off + i;
+        if (mask[g] & SELF_SOLID) continue;
+        const double x = ux[g], y = uy[g];
+        umax = fmax(umax, sqrt(x * x + y * y));
+        if (sx) e1 = fmax(e1, fmax(fabs(x - (double)sx[g]), fabs(y - (double)sy[g])));
+    }
+    __shared__ double sh[DIAG_THREADS];
+    umax = block_max(umax, sh);
+    e1 = block_max(e1, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = umax;
+        partials[2 * blockIdx.x + 1] = e1;
+    }
+}
+
+__global__ void max_final_kernel(const double *partials, int n_doms, double *out, int has_snap) {
+    const int dom = blockIdx.x * blockDim.x + threadIdx.x;
+    if (dom >= n_doms) return;
+    double a = 0.0, e = 0.0;
+    for (int b = 0; b < DIAG_BLOCKS; b++) {
+        a = fmax(a, partials[2 * (dom * DIAG_BLOCKS + b)]);
+        e = fmax(e, partials[2 * (dom * DIAG_BLOCKS + b) + 1]);
+    }
+    out[2 * dom] = a;
+    out[2 * dom + 1] = has_snap ? e : __builtin_nan("");
+}
+
+template <class AT>
+__global__ void velocity_copy_kernel(const DomDev *doms, int dom, const uint16_t *mask,
+                                     const AT *ux, const AT *uy, double *ox, double *oy) {
+    const DomDev &D = doms[dom];
+    const size_t nn = (size_t)D.nx * D.ny;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t g = D.off + i;
+        const bool fl = !(mask[g] & SELF_SOLID);
+        if (ox) ox[i] = fl ? (double)ux[g] : 0.0;
+        if (oy) oy[i] = fl ? (double)uy[g] : 0.0;
+    }
+}
+
+// Colour masses inside and outside a region (the sums of Eq. 47)
+template <class T>
+__global__ __launch_bounds__(DIAG_THREADS) void region_mass_kernel(
+    const StepArgs<T, typename Codec<T>::AT> A, int dom, const uint8_t *region, double *partials) {
+    using AT = typename Codec<T>::AT;
+    DomC &D = *(DomC *)(A.doms + dom);
+    const size_t nn = (size_t)D.nx * D.ny;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t i = blockIdx.x * (size_t)DIAG_THREADS + threadIdx.x; i < nn; i += (size_t)DIAG_BLOCKS * DIAG_THREADS) {
+        const uint32_t m = A.mask[D.off + i];
+        if (m & SELF_SOLID) continue;
+        AT d[9], rR, rB;
+        gather_global(A, D, (int)(i % D.nx), (int)(i / D.nx), m, d, rR, rB);
+        const int k = region[i] ? 0 : 1;
+        s[k] += (double)rR;
+        s[2 + k] += (double)rB;
+    }
+    __shared__ double sh[DIAG_THREADS];
+    for (int k = 0; k < 4; k++) {
+        const double v = block_sum(s[k], sh);
+        if (threadIdx.x == 0) partials[4 * blockIdx.x + k] = v;
+    }
+}
+
+__global__ void sum4_final_kernel(const double *partials, double *out) {
+    const int k = threadIdx.x;
+    if (k >= 4) return;
+    double v = 0.0;
+    for (int b = 0; b < DIAG_BLOCKS; b++) v += partials[4 * b + k];
+    out[k] = v;
+}
+
+// rho^N of node (x, y) from its gathered densities; 0 on solid nodes
+template <class T>
+__device__ double rho_n_at(const StepArgs<T, typename Codec<T>::AT> &A, DomC &D, int x, int y) {
+    using AT = typename Codec<T>::AT;
+    const uint32_t m = A.mask[D.off + (size_t)y * D.nx + x];
+    if (m & SELF_SOLID) return 0.0;
+    AT d[9], rR, rB;
+    gather_global(A, D, x, y, m, d, rR, rB);
+    return ((double)rR - (double)rB) / ((double)rR + (double)rB);
+}
+
+// One block per listed row: the first x with rho^N(x) > 0 >= rho^N(x + 1), interpolated
+// linearly to x + rho^N(x) / (rho^N(x) - rho^N(x + 1))
+template <class T>
+__global__ __launch_bounds__(DIAG_THREADS) void crossing_kernel(
+    const StepArgs<T, typename Codec<T>::AT> A, int dom, const int *rows, double *out) {
+    DomC &D = *(DomC *)(A.doms + dom);
+    const int y = rows[blockIdx.x];
+    __shared__ int first;
+    if (threadIdx.x == 0) first = D.nx;
+    __syncthreads();
+    if (y >= 0 && y < D.ny) {
+        for (int x = threadIdx.x; x < D.nx - 1; x += DIAG_THREADS) {
+            if (x >= first) break;
+            if (rho_n_at(A, D, x, y) > 0.0 && rho_n_at(A, D, x + 1, y) <= 0.0) atomicMin(&first, x);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = __builtin_nan("");
+        if (y >= 0 && y < D.ny && first < D.nx) {
+            const double a = rho_n_at(A, D, first, y), b = rho_n_at(A, D, first + 1, y);
+            r = first + a / (a - b);
+        }
+        out[blockIdx.x] = r;
+    }
+}
+
 // ------------------------------------------------------------------- launchers
 template <class T>
 static hipError_t step_t(const void *args, int n_items, int waves, hipStream_t s) {
@@ -1012,6 +1167,106 @@ hipError_t launch_mass(int storage, const void *args, int n_doms, const int *, d
         case 2: return mass_t<__half>(args, n_doms, partials, bpd, out, s);
         case 3: return mass_t<C16>(args, n_doms, partials, bpd, out, s);
     }
+    return hipErrorInvalidValue;
+}
+
+template <class T>
+static const StepArgs<T, typename Codec<T>::AT> &args_of(const void *a) {
+    return *static_cast<const StepArgs<T, typename Codec<T>::AT> *>(a);
+}
+
+template <class T>
+static hipError_t velocity_stats_t(const void *args, int n_doms, const void *u, const void *snap,
+                                   double *partials, double *out, hipStream_t s) {
+    using AT = typename Codec<T>::AT;
+    const auto &A = args_of<T>(args);
+    const size_t stride = A.c_plane_bytes / sizeof(AT);
+    const AT *ux = static_cast<const AT *>(u), *sx = static_cast<const AT *>(snap);
+    hipLaunchKernelGGL(velocity_stats_kernel<AT>, dim3(n_doms * DIAG_BLOCKS), dim3(DIAG_THREADS), 0, s,
+                       A.doms, A.mask, ux, ux + stride, sx, sx ? sx + stride : nullptr, partials);
+    hipLaunchKernelGGL(max_final_kernel, dim3((n_doms + 63) / 64), dim3(64), 0, s, partials, n_doms,
+                       out, snap != nullptr);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t velocity_copy_t(const void *args, int dom, const void *u, double *ox, double *oy,
+                                  hipStream_t s) {
+    using AT = typename Codec<T>::AT;
+    const auto &A = args_of<T>(args);
+    const size_t stride = A.c_plane_bytes / sizeof(AT);
+    const AT *ux = static_cast<const AT *>(u);
+    hipLaunchKernelGGL(velocity_copy_kernel<AT>, dim3(1024), dim3(256), 0, s, A.doms, dom, A.mask, ux,
+                       ux + stride, ox, oy);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t region_mass_t(const void *args, int dom, const uint8_t *region, double *partials,
+                                double *out, hipStream_t s) {
+    hipLaunchKernelGGL(region_mass_kernel<T>, dim3(DIAG_BLOCKS), dim3(DIAG_THREADS), 0, s, args_of<T>(args),
+                       dom, region, partials);
+    hipLaunchKernelGGL(sum4_final_kernel, dim3(1), dim3(64), 0, s, partials, out);
+    return hipGetLastError();
+}
+
+template <class T>
+static hipError_t crossings_t(const void *args, int dom, const int *rows, int n_rows, double *out,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(crossing_kernel<T>, dim3(n_rows), dim3(DIAG_THREADS), 0, s, args_of<T>(args), dom,
+                       rows, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity_stats(int storage, const void *args, int n_doms, const void *u,
+                                 const void *snap, double *partials, double *out, hipStream_t s) {
+#define CALL(T) velocity_stats_t<T>(args, n_doms, u, snap, partials, out, s)
+    switch (storage) {
+        case 0: return CALL(double);
+        case 1: return CALL(float);
+        case 2: return CALL(__half);
+        case 3: return CALL(C16);
+    }
+#undef CALL
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_velocity_copy(int storage, const void *args, int dom, const void *u, double *ox,
+                                double *oy, hipStream_t s) {
+#define CALL(T) velocity_copy_t<T>(args, dom, u, ox, oy, s)
+    switch (storage) {
+        case 0: return CALL(double);
+        case 1: return CALL(float);
+        case 2: return CALL(__half);
+        case 3: return CALL(C16);
+    }
+#undef CALL
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_region_mass(int storage, const void *args, int dom, const uint8_t *region,
+                              double *partials, double *out, hipStream_t s) {
+#define CALL(T) region_mass_t<T>(args, dom, region, partials, out, s)
+    switch (storage) {
+        case 0: return CALL(double);
+        case 1: return CALL(float);
+        case 2: return CALL(__half);
+        case 3: return CALL(C16);
+    }
+#undef CALL
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_crossings(int storage, const void *args, int dom, const int *rows, int n_rows,
+                            double *out, hipStream_t s) {
+#define CALL(T) crossings_t<T>(args, dom, rows, n_rows, out, s)
+    switch (storage) {
+        case 0: return CALL(double);
+        case 1: return CALL(float);
+        case 2: return CALL(__half);
+        case 3: return CALL(C16);
+    }
+#undef CALL
     return hipErrorInvalidValue;
 }
 

@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbmcg.so")
 
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "c16": 3}
-FIELD_RHO_R, FIELD_RHO_B, FIELD_POPS = 1, 2, 4
+FIELD_RHO_R, FIELD_RHO_B, FIELD_POPS, FIELD_UX, FIELD_UY = 1, 2, 4, 8, 16
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
@@ -52,6 +52,11 @@ PROTOTYPES = {
     "lbm_state_size": (C.c_size_t, [C.c_void_p]),
     "lbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_diag_bytes": (C.c_size_t, [C.c_void_p]),
+    "lbm_diag_attach": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "lbm_diag_velocity": (C.c_int, [C.c_void_p, C.c_int, _dp]),
+    "lbm_diag_region_mass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, _dp]),
+    "lbm_diag_crossings": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int, _dp]),
     "lbm_last_error": (C.c_char_p, []),
     "lbm_destroy": (None, [C.c_void_p]),
 }
@@ -174,7 +179,9 @@ class Lattice:
         """FP64 device tensor (planes, ny, nx) of the selected quantities."""
         s = self.setups[dom]
         ny, nx = s.solid.shape
-        planes = (which & 1) + ((which >> 1) & 1) + 18 * ((which >> 2) & 1)
+        planes = (which & 1) + ((which >> 1) & 1) + 18 * ((which >> 2) & 1) + ((which >> 3) & 1) + ((which >> 4) & 1)
+        if which & (FIELD_UX | FIELD_UY):
+            self._diag()
         out = self.torch.empty((planes, ny, nx), dtype=self.torch.float64, device=self.device)
         _check(load_library().lbm_read_fields(self._h, dom, which, out.data_ptr(), out.numel()))
         return out
@@ -195,6 +202,46 @@ class Lattice:
         out = np.empty(2 * len(self.setups))
         _check(load_library().lbm_mass(self._h, _ptr(out, C.c_double)))
         return out.reshape(-1, 2)
+
+    def velocity(self, dom: int = 0):
+        """(u_x, u_y) of Eq. 17 that the next collision uses, FP64, solid nodes 0."""
+        t = self.read(dom, FIELD_UX | FIELD_UY)
+        self.synchronize()
+        a = t.cpu().numpy()
+        return a[0], a[1]
+
+    # ------------------------------------------------------------- diagnostics
+    def _diag(self):
+        if getattr(self, "diag_buf", None) is None:
+            L = load_library()
+            n = int(L.lbm_diag_bytes(self._h))
+            self.diag_buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+            _check(L.lbm_diag_attach(self._h, self.diag_buf.data_ptr(), n))
+
+    def velocity_stats(self, snapshot: bool = False) -> np.ndarray:
+        """(n_domains, 2): |u|max (Eq. 46) and the largest velocity-component change since the
+        last snapshot (Eq. 45 with a 500-step gap; NaN before the first snapshot)."""
+        self._diag()
+        out = np.empty(2 * len(self.setups))
+        _check(load_library().lbm_diag_velocity(self._h, int(bool(snapshot)), _ptr(out, C.c_double)))
+        return out.reshape(-1, 2)
+
+    def region_mass(self, dom: int, region) -> np.ndarray:
+        """[rho_R inside, rho_R outside, rho_B inside, rho_B outside] for a (ny, nx) region mask."""
+        self._diag()
+        r = self.torch.as_tensor(np.ascontiguousarray(region, dtype=np.uint8), device=self.device)
+        out = np.empty(4)
+        _check(load_library().lbm_diag_region_mass(self._h, dom, r.data_ptr(), _ptr(out, C.c_double)))
+        return out
+
+    def crossings(self, dom: int, rows) -> np.ndarray:
+        """First rho^N > 0 -> <= 0 crossing x along each row (NaN where none)."""
+        self._diag()
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        out = np.empty(len(rows))
+        _check(load_library().lbm_diag_crossings(self._h, dom, _ptr(rows, C.c_int32), len(rows),
+                                                 _ptr(out, C.c_double)))
+        return out
 
     # -------------------------------------------------------------- checkpoints
     def save_state(self):
