@@ -132,11 +132,12 @@ int lbm_mass(lbm_ctx *ctx, double *out_host);
 /* Number of time steps taken so far. */
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 
-/* Tile shape of the fused step: `chunk_rows` rows of a 54-column strip per work item
- * (multiple of 4, >= 8; 0 = built-in choice) and `waves` tile rows advanced per iteration
- * (4 or 8; 0 = built-in).  Rebuilds the schedule; results do not depend on the tile shape.
- * Synchronises the stream. */
-int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves);
+/* Tile shape of the fused step: `chunk_rows` rows of a strip per work item (multiple of 4,
+ * >= 8; 0 = built-in choice), `waves` tile rows advanced per iteration (4 or 8; 0 = built-in)
+ * and `cols` wavefronts side by side in a tile row (1: 64-column tiles with 54 output columns,
+ * 2: 128-column tiles with 118; 0 = built-in; 8 x 2 is not provided).  Rebuilds the schedule;
+ * results do not depend on the tile shape.  Synchronises the stream. */
+int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves, int cols);
 
 /* Checkpoint: copy the complete mutable state (state buffer contents plus step parity) to
  * `dst_dev` (device, lbm_state_size bytes) or restore it from `src_dev`.  Stream-ordered. */

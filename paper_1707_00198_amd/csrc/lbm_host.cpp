@@ -61,7 +61,9 @@ struct Layout {
            mass_out = 0, flag = 0, scratch_bytes = 0;
 };
 
-int strips_of(const lbm_domain_desc &d) { return (d.nx + TILE_OUT - 1) / TILE_OUT; }
+int strips_of(const lbm_domain_desc &d, int cols = 1) {
+    return (d.nx + tile_out(cols) - 1) / tile_out(cols);
+}
 
 Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
     Layout L;
@@ -248,6 +250,7 @@ struct lbm_ctx {
     std::vector<WorkItem> items;
     int chunk_rows = 0;
     int waves = 0;    // wavefronts (tile rows advanced per iteration) of the step kernel
+    int cols = 1;     // wavefronts side by side in a tile row (tile width 64 cols)
     int parity = 0;   // buffer holding the current state
     int own = 1;      // current state is a node-local snapshot
     int64_t steps = 0;
@@ -356,17 +359,17 @@ AnyArgs make_diag_args(const lbm_ctx *c) {
 // stream a narrow band of every plane, which measured markedly faster than a strip at a time.
 // A domain with more items than one run is cut into strip groups of about one run each, so
 // that every XCD works through a compact region and neighbouring strips share its L2.
-std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk) {
+std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk, int cols) {
     size_t total = 0;
     for (const auto &q : d) {
         const int nch = std::max(1, (q.ny + chunk - 1) / chunk);
-        total += (size_t)strips_of(q) * nch;
+        total += (size_t)strips_of(q, cols) * nch;
     }
     const size_t run = std::max<size_t>(1, total / 8);
     std::vector<WorkItem> out;
     out.reserve(total);
     for (int i = 0; i < (int)d.size(); i++) {
-        const int ny = d[i].ny, S = strips_of(d[i]);
+        const int ny = d[i].ny, S = strips_of(d[i], cols);
         const int nch = std::max(1, (ny + chunk - 1) / chunk);
         const int ch = ((ny + nch - 1) / nch + 3) / 4 * 4;
         const size_t items = (size_t)S * nch;
@@ -376,7 +379,7 @@ std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chu
             for (int k = 0; k < nch; k++) {
                 const int y0 = k * ch, y1 = std::min(ny, y0 + ch);
                 if (y0 >= y1) continue;
-                for (int s = s0; s < s1; s++) out.push_back(WorkItem{i, s * TILE_OUT, y0, y1});
+                for (int s = s0; s < s1; s++) out.push_back(WorkItem{i, s * tile_out(cols), y0, y1});
             }
         }
     }
@@ -386,16 +389,19 @@ std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chu
 // Tallest chunk, up to 64 rows, that still yields 4096 work items.  Taller chunks repeat fewer
 // halo rows, but with the band-major order shorter bands measured faster on wide domains
 // (16384 x 512: 32 rows best), and enough items keep every CU busy on small ones.
-int auto_chunk(const std::vector<lbm_domain_desc> &d) {
+int auto_chunk(const std::vector<lbm_domain_desc> &d, int cols) {
     const int cands[] = {64, 48, 32, 24, 16, 12, 8};
     for (int ch : cands)
-        if (build_items(d, ch).size() >= 4096) return ch;
+        if (build_items(d, ch, cols).size() >= 4096) return ch;
     return 8;
 }
 
 // Blocks of 4 tile rows (one wavefront per SIMD) measured at least as fast as blocks of 8 for
 // every storage type.
 int default_waves(int) { return 4; }
+// One-wavefront tiles.  Tiles two wavefronts wide (118 output columns of 128) repeat fewer
+// halo columns but measured 3-5 % slower on the sweep (8-wavefront barriers, 2 blocks per CU).
+int default_cols(int) { return 1; }
 
 int upload_items(lbm_ctx *c) {
     if (c->items.size() > c->L.items_cap) return fail(LBM_EINVAL, "work-item table overflow");
@@ -533,9 +539,10 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     c->L = L;
     c->desc.assign(domains, domains + n);
     c->doms.resize(n);
-    c->chunk_rows = auto_chunk(c->desc);
     c->waves = default_waves(storage);
-    c->items = build_items(c->desc, c->chunk_rows);
+    c->cols = default_cols(storage);
+    c->chunk_rows = auto_chunk(c->desc, c->cols);
+    c->items = build_items(c->desc, c->chunk_rows, c->cols);
     if (hipHostMalloc((void **)&c->mass_host, (2 * (size_t)n + 2) * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->flag_host, 64) != hipSuccess) {
         delete c;
@@ -577,7 +584,7 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
     if (n_steps < 0) return fail(LBM_EINVAL, "negative step count");
     for (int64_t k = 0; k < n_steps; k++) {
         AnyArgs a = make_args(c, c->parity);
-        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->stream));
+        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->cols, c->stream));
         c->parity ^= 1;
         c->own = 0;
         c->steps++;
@@ -606,7 +613,7 @@ int lbm_read_fields(lbm_ctx *c, int domain, uint32_t which, double *out_dev, siz
     }
     if (which & 24u) {
         AnyArgs da = make_diag_args(c);
-        HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->stream));
+        HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->stream));
         double *ox = (which & 8u) ? out_dev + (p++) * nn : nullptr;
         double *oy = (which & 16u) ? out_dev + p * nn : nullptr;
         HIP_OK(launch_velocity_copy(c->storage, a.bytes, domain, c->diag + diag_layout(c).u, ox, oy,
@@ -633,15 +640,19 @@ int lbm_mass(lbm_ctx *c, double *out_host) {
 
 int64_t lbm_steps_taken(const lbm_ctx *c) { return c ? c->steps : -1; }
 
-int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves) {
+int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves, int cols) {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (chunk_rows != 0 && (chunk_rows < 8 || chunk_rows % 4))
         return fail(LBM_EINVAL, "chunk rows must be 0 or a multiple of 4 >= 8");
     if (waves != 0 && waves != 4 && waves != 8) return fail(LBM_EINVAL, "waves must be 0, 4 or 8");
+    if (cols != 0 && cols != 1 && cols != 2) return fail(LBM_EINVAL, "cols must be 0, 1 or 2");
+    const int w = waves ? waves : default_waves(c->storage), k = cols ? cols : default_cols(c->storage);
+    if (w == 8 && k == 2) return fail(LBM_EINVAL, "tiles of 8 x 2 wavefronts are not provided");
     HIP_OK(hipStreamSynchronize(c->stream));
-    c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc);
-    c->waves = waves ? waves : default_waves(c->storage);
-    c->items = build_items(c->desc, c->chunk_rows);
+    c->waves = w;
+    c->cols = k;
+    c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc, c->cols);
+    c->items = build_items(c->desc, c->chunk_rows, c->cols);
     return upload_items(c);
 }
 
@@ -703,7 +714,7 @@ int lbm_diag_velocity(lbm_ctx *c, int snapshot, double *out_host) {
     if (!c->diag) return fail(LBM_ESTATE, "no diagnostics buffer attached (lbm_diag_attach)");
     const DiagLayout DL = diag_layout(c);
     AnyArgs da = make_diag_args(c);
-    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->stream));
+    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->stream));
     double *res = reinterpret_cast<double *>(c->diag + DL.res);
     HIP_OK(launch_velocity_stats(c->storage, da.bytes, c->n, c->diag + DL.u,
                                  c->snap_valid ? c->diag + DL.snap : nullptr,

@@ -17,7 +17,8 @@ constexpr uint32_t SOLID_BND = 1u << 10;  // solid node with a fluid neighbour
 constexpr int TILE_LANES = 64;     // columns per tile row (one wavefront)
 constexpr int HALO = 5;            // halo columns per side: the step's dependency radius next to
                                    // walls is 4, plus one column for the colour-state stencil
-constexpr int TILE_OUT = TILE_LANES - 2 * HALO;  // output columns per tile
+constexpr int TILE_OUT = TILE_LANES - 2 * HALO;  // output columns of a one-wavefront-wide tile
+inline int tile_out(int cols) { return TILE_LANES * cols - 2 * HALO; }
 
 // Per-domain parameters in one arithmetic type, with the constant factors of the collision
 // precomputed: ke = 6 (1 - s_e / 2), keps = 6 (1 - s_eps / 2), kq = 1 - s_q / 2 (the forcing
@@ -85,7 +86,8 @@ struct StepArgs {
 };
 
 // Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16, 3 c16.
-hipError_t launch_step(int storage, const void *args, int n_items, int waves, hipStream_t s);
+// waves x cols wavefronts per block: (4, 1), (8, 1) or (4, 2); a tile is 64 cols columns wide
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols, hipStream_t s);
 hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, uint32_t which,
                        double *out, hipStream_t s);
 hipError_t launch_mass(int storage, const void *args, int n_doms, const int *dom_nodes_begin,

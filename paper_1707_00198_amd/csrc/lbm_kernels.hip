@@ -501,22 +501,24 @@ struct Buf<uint16_t> {
 };
 
 // ------------------------------------------------------------------ the step kernel
-// R wavefronts per block, one tile row each.  In iteration r the block runs stages B..E on
+// R x C wavefronts per block: R tile rows, each C wavefronts (64 C columns) wide.  In iteration
+// r the block runs stages B..E on
 // rows r + R - 1 + w, r + R - 2 + w, r + R - 3 + w and r + w (w = wavefront), then stage A of
 // the next iteration's rows r + 2R + w, and issues the loads for the stage A after that.  Stage E
 // of a row runs on the thread that gathered the row one iteration earlier.  LDS rings hold 2R
 // rows.
-template <class T, int R>
-__global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ? 4 : 2) void step_kernel(const StepArgs<T, typename Codec<T>::AT> A) {
+template <class T, int R, int C>
+__global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 4 ? 4 : 2) void step_kernel(const StepArgs<T, typename Codec<T>::AT> A) {
     using AT = typename Codec<T>::AT;
     constexpr int Q = 2 * R;
+    constexpr int TL = TILE_LANES * C;  // columns of the window: C wavefronts side by side
     constexpr uint32_t SB = sizeof(T), CB = sizeof(AT);
-    __shared__ AT s_rn[Q][TILE_LANES];
-    __shared__ AT s_nx[Q][TILE_LANES], s_ny[Q][TILE_LANES];
-    __shared__ AT s_gx[Q][TILE_LANES], s_gy[Q][TILE_LANES];
-    __shared__ AT s_c[Q][TILE_LANES], s_vx[Q][TILE_LANES], s_vy[Q][TILE_LANES];
-    __shared__ AT s_wx[Q][TILE_LANES], s_wy[Q][TILE_LANES];
-    __shared__ uint16_t s_m[Q][TILE_LANES];
+    __shared__ AT s_rn[Q][TL];
+    __shared__ AT s_nx[Q][TL], s_ny[Q][TL];
+    __shared__ AT s_gx[Q][TL], s_gy[Q][TL];
+    __shared__ AT s_c[Q][TL], s_vx[Q][TL], s_vy[Q][TL];
+    __shared__ AT s_wx[Q][TL], s_wy[Q][TL];
+    __shared__ uint16_t s_m[Q][TL];
 
     // work item: wave-uniform
     const WorkItem *itp = A.items + item_of_block(blockIdx.x, A.n_items);
@@ -526,8 +528,8 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
     DomC &D = *(DomC *)(A.doms + dom);
     // the wavefront index is uniform within a wavefront: row indices, row-range tests and LDS
     // row slots then live in scalar registers
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / TILE_LANES);
-    const int lane = threadIdx.x % TILE_LANES;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / TL);
+    const int lane = threadIdx.x % TL;
     const int base = x0 - HALO;
     const int X = base + lane;
     // Node column of the lane: periodic in x, or clamped to the edge columns of an open x axis.
@@ -536,11 +538,11 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
     // each stage that writes a stencil field they copy the edge lane's value (edge_lane >= 0),
     // which only work items touching an open edge do.
     const int xe = D.open_x ? min(max(X, 0), D.nx - 1) : wrap(X, D.nx);
-    const bool edge_item = D.open_x && (base < 0 || base + TILE_LANES > D.nx);
+    const bool edge_item = D.open_x && (base < 0 || base + TL > D.nx);
     const int edge_lane = xe != X && D.open_x ? xe - base : -1;
     const int lanes_of[3] = {lane - 1, lane, lane + 1};
-    const bool out_lane = lane >= HALO && lane < TILE_LANES - HALO && X < D.nx;
-    const bool gather_lane = lane >= 1 && lane < TILE_LANES - 1;
+    const bool out_lane = lane >= HALO && lane < TL - HALO && X < D.nx;
+    const bool gather_lane = lane >= 1 && lane < TL - 1;
     ParC<AT> &P = par(D, AT());
     const AT eps = P.eps;
     const int r_first = y0 - HALO + 1 - R;  // first stage A row is y0 - 4
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         Buf<AT>::store(c_out, vc, 2 * CP, by);
     };
 
-    auto replicate = [&](AT (*f)[TILE_LANES], int sl) {
+    auto replicate = [&](AT (*f)[TL], int sl) {
         if (edge_item && edge_lane >= 0) f[sl][lane] = f[sl][edge_lane];
     };
 
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         {
             const int yb = r + R - 1 + w;
             const int sl = yb & (Q - 1);
-            if (lane >= 2 && lane < TILE_LANES - 2 && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
+            if (lane >= 2 && lane < TL - 2 && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
                 const uint32_t m = s_m[sl][lane];
                 if (m & SOLID_BND) {
                     AT num = AT(0), den = AT(0);
@@ -707,7 +709,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         {
             const int yc = r + R - 2 + w;
             const int sl = yc & (Q - 1);
-            if (lane >= 3 && lane < TILE_LANES - 3 && yc >= y0 - HALO + 3 && yc < y1 + HALO - 3) {
+            if (lane >= 3 && lane < TL - 3 && yc >= y0 - HALO + 3 && yc < y1 + HALO - 3) {
                 const uint32_t m = s_m[sl][lane];
                 AT gx = AT(0), gy = AT(0), nx = AT(0), ny = AT(0);
                 if (!(m & SELF_SOLID)) {
@@ -740,7 +742,7 @@ __global__ __launch_bounds__(TILE_LANES *R, sizeof(typename Codec<T>::AT) == 4 ?
         {
             const int yd = r + R - 3 + w;
             const int sl = yd & (Q - 1);
-            if (lane >= 4 && lane < TILE_LANES - 4 && yd >= y0 - 1 && yd < y1 + 1) {
+            if (lane >= 4 && lane < TL - 4 && yd >= y0 - 1 && yd < y1 + 1) {
                 const uint32_t m = s_m[sl][lane];
                 if (m & SOLID_BND) {
                     AT numx = AT(0), numy = AT(0), den = AT(0);
@@ -1107,22 +1109,24 @@ __global__ __launch_bounds__(DIAG_THREADS) void crossing_kernel(
 
 // ------------------------------------------------------------------- launchers
 template <class T>
-static hipError_t step_t(const void *args, int n_items, int waves, hipStream_t s) {
+static hipError_t step_t(const void *args, int n_items, int waves, int cols, hipStream_t s) {
     const auto &A = *static_cast<const StepArgs<T, typename Codec<T>::AT> *>(args);
-    if (waves == 8)
-        hipLaunchKernelGGL((step_kernel<T, 8>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
+    if (cols == 2)
+        hipLaunchKernelGGL((step_kernel<T, 4, 2>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
+    else if (waves == 8)
+        hipLaunchKernelGGL((step_kernel<T, 8, 1>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
     else
-        hipLaunchKernelGGL((step_kernel<T, 4>), dim3(n_items), dim3(TILE_LANES * 4), 0, s, A);
+        hipLaunchKernelGGL((step_kernel<T, 4, 1>), dim3(n_items), dim3(TILE_LANES * 4), 0, s, A);
     return hipGetLastError();
 }
 
-hipError_t launch_step(int storage, const void *args, int n_items, int waves, hipStream_t s) {
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (storage) {
-        case 0: return step_t<double>(args, n_items, waves, s);
-        case 1: return step_t<float>(args, n_items, waves, s);
-        case 2: return step_t<__half>(args, n_items, waves, s);
-        case 3: return step_t<C16>(args, n_items, waves, s);
+        case 0: return step_t<double>(args, n_items, waves, cols, s);
+        case 1: return step_t<float>(args, n_items, waves, cols, s);
+        case 2: return step_t<__half>(args, n_items, waves, cols, s);
+        case 3: return step_t<C16>(args, n_items, waves, cols, s);
     }
     return hipErrorInvalidValue;
 }

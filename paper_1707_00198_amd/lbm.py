@@ -48,7 +48,7 @@ PROTOTYPES = {
     "lbm_read_fields": (C.c_int, [C.c_void_p, C.c_int, C.c_uint32, C.c_void_p, C.c_size_t]),
     "lbm_mass": (C.c_int, [C.c_void_p, _dp]),
     "lbm_steps_taken": (C.c_int64, [C.c_void_p]),
-    "lbm_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
+    "lbm_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
     "lbm_state_size": (C.c_size_t, [C.c_void_p]),
     "lbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -168,8 +168,8 @@ class Lattice:
     def steps(self) -> int:
         return int(load_library().lbm_steps_taken(self._h))
 
-    def set_tile(self, chunk_rows: int = 0, waves: int = 0):
-        _check(load_library().lbm_set_tile(self._h, int(chunk_rows), int(waves)))
+    def set_tile(self, chunk_rows: int = 0, waves: int = 0, cols: int = 0):
+        _check(load_library().lbm_set_tile(self._h, int(chunk_rows), int(waves), int(cols)))
 
     def synchronize(self):
         self.stream.synchronize()

@@ -147,14 +147,26 @@ def test_mass_fp64_matches_oracle_and_is_conserved():
 
 
 def test_chunking_does_not_change_results():
+    """Chunk height and tile shape (4 x 1, 8 x 1, 4 x 2 wavefronts) change only the schedule."""
     s = small_cases()[1]
-    a = lattice([s])
-    a.set_tile(8, 4)
-    pa = a.step(40).pops(0)
-    b = lattice([s])
-    b.set_tile(64, 8)
-    pb = b.step(40).pops(0)
-    assert np.array_equal(pa, pb)
+    ref = None
+    for chunk, waves, cols in ((8, 4, 1), (64, 8, 1), (12, 4, 2), (64, 4, 2)):
+        lat = lattice([s])
+        lat.set_tile(chunk, waves, cols)
+        p = lat.step(40).pops(0)
+        if ref is None:
+            ref = p
+        assert np.array_equal(p, ref), (chunk, waves, cols)
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_parity_fp64_two_wavefront_tiles(idx):
+    """The 128-column tiles (two wavefronts per row, the default of the 4-byte storages) on the
+    FP64 path against the oracle, including open channels whose edge columns are replicated."""
+    s = small_cases()[idx]
+    lat = lattice([s])
+    lat.set_tile(0, 4, 2)
+    assert_parity(lat.step(200).pops(0), oracle_for(s).step(200).pops(), what=f"{s.name} 4x2")
 
 
 def test_checkpoint_roundtrip_is_bitwise():
