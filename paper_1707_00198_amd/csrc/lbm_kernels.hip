@@ -519,6 +519,8 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     __shared__ AT s_c[Q][TL], s_vx[Q][TL], s_vy[Q][TL];
     __shared__ AT s_wx[Q][TL], s_wy[Q][TL];
     __shared__ uint16_t s_m[Q][TL];
+    // per row slot and wavefront column: the row has an outermost solid node in that column
+    __shared__ int s_wall[Q][C];
 
     // work item: wave-uniform
     const WorkItem *itp = A.items + item_of_block(blockIdx.x, A.n_items);
@@ -564,30 +566,47 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     // Prefetched inputs of one stage A row ya: pulled populations (pulls from solid nodes
     // redirected to the node's own opposite population), its class word and the wall normal on
     // outermost fluid nodes; qm carries the class word of the row, loaded by the previous
-    // prefetch.  The colour state of row ya + 1 is loaded separately, in stage E before the
-    // stores: vector memory instructions complete in order, stores included, so the colour
-    // wait in the next stage D then never waits for stores issued just before it.
-    T pf[9];
-    uint32_t pm = SELF_SOLID, qm = 0;
-    AT pc = AT(0), pvx = AT(0), pvy = AT(0), pwx = AT(0), pwy = AT(0);
-    auto load_colour = [&](int yc) {
+    // prefetch.  The set is issued one iteration before its stage A.  (A second set issued two
+    // iterations ahead was measured slower: with the stores in between, the vector memory
+    // operations in flight exceed what the wait counter expresses, and the compiler then waits
+    // for the newest stores.)  The colour state that stage D puts into LDS for a stage A row is
+    // loaded at the top of the iteration before: vector memory instructions complete in order,
+    // stores included, so it then has a full iteration (and never waits for the stores of the
+    // stage E in between).  Two colour register sets alternate between iterations (the loop is
+    // unrolled twice).
+    struct Pre {
+        T f[9];
+        uint32_t m;
+        AT wx, wy;
+    };
+    Pre pre;
+#pragma unroll
+    for (int a = 0; a < 9; a++) pre.f[a] = T{};
+    pre.m = SELF_SOLID;
+    pre.wx = pre.wy = AT(0);
+    uint32_t qm = 0;
+    struct Colour {
+        AT c, vx, vy;
+    };
+    Colour cset[2] = {{AT(0), AT(0), AT(0)}, {AT(0), AT(0), AT(0)}};
+    auto load_colour = [&](int yc, Colour &cs) {
         const uint32_t vo = row_ok_c(yc) ? node_of(yc) * CB : NOWHERE;
-        pc = Buf<AT>::load(c_in, vo, 0);
-        pvx = Buf<AT>::load(c_in, vo, CP);
-        pvy = Buf<AT>::load(c_in, vo, 2 * CP);
+        cs.c = Buf<AT>::load(c_in, vo, 0);
+        cs.vx = Buf<AT>::load(c_in, vo, CP);
+        cs.vy = Buf<AT>::load(c_in, vo, 2 * CP);
     };
     auto load_mask = [&](int y) {
         qm = Buf<uint16_t>::load(r_mask, row_ok_a(y) ? node_of(y) * 2u : NOWHERE, 0);
     };
-    auto prefetch = [&](int ya) {
+    auto prefetch = [&](int ya, Pre &p) {
         const bool ok = row_ok_a(ya);
         const uint32_t m = ok ? qm : SELF_SOLID;
         const bool act = gather_lane && !(m & SELF_SOLID);
         Nbr nb = make_nbr(D, xe, wrap(ya, D.ny));
         const uint32_t self = (uint32_t)nb.row[1] + (uint32_t)xe;
         const uint32_t vw = act && (m & FLUID_BND) ? self * CB : NOWHERE;
-        pwx = Buf<AT>::load(r_ns, vw, 0);
-        pwy = Buf<AT>::load(r_ns, vw, A.ns_stride_bytes);
+        p.wx = Buf<AT>::load(r_ns, vw, 0);
+        p.wy = Buf<AT>::load(r_ns, vw, A.ns_stride_bytes);
         // snapshot state: every population is the node's own, none bounces
         const uint32_t solid_nbrs = A.own ? 0u : m;
         if (A.own) {
@@ -604,17 +623,17 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
             uint32_t vo = (uint32_t)pull_src(nb, a) * SB + up;
             if (a > 0 && !pull_outside(nb, a) && (solid_nbrs & (1u << (OPP[a] - 1))))
                 vo = self * SB + (2u * FP - up);
-            pf[a] = Buf<T>::load(f_in, act ? vo : NOWHERE, (uint32_t)lo * FP);
+            p.f[a] = Buf<T>::load(f_in, act ? vo : NOWHERE, (uint32_t)lo * FP);
         }
-        pm = m;
+        p.m = m;
         load_mask(ya + R);
     };
     // colour row yc into the LDS ring
-    auto put_colour = [&](int yc) {
+    auto put_colour = [&](int yc, const Colour &cs) {
         const int sl = yc & (Q - 1);
-        s_c[sl][lane] = pc;
-        s_vx[sl][lane] = pvx;
-        s_vy[sl][lane] = pvy;
+        s_c[sl][lane] = cs.c;
+        s_vx[sl][lane] = cs.vx;
+        s_vy[sl][lane] = cs.vy;
     };
     // one row of outputs: populations, then the colour state (c, vx, vy)
     auto store_row = [&](uint32_t vf, uint32_t vc, const AT (&o)[9], AT c, AT bx, AT by) {
@@ -635,15 +654,18 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     for (int a = 0; a < 9; a++) d[a] = dn[a] = AT(0);
 
     // ---- A: gather, densities, colour indicator of row ya into LDS and dn / rRn / rBn / rNn
-    auto stage_a = [&](int ya) {
+    auto stage_a = [&](int ya, const Pre &p) {
         const int sl = ya & (Q - 1);
-        const uint32_t m = pm;
+        const uint32_t m = p.m;
         AT rn = AT(0);
+        // decoded on every lane (values of lanes without an output node are never stored):
+        // a path that left the prefetched registers unread would make the compiler take them
+        // as possibly in flight, and wait for the whole prefetch wherever it reuses one
+#pragma unroll
+        for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(p.f[a], a);
         if (gather_lane && !(m & SELF_SOLID)) {
             const int yw = wrap(ya, D.ny);
             const Nbr nb = make_nbr(D, xe, yw);
-#pragma unroll
-            for (int a = 0; a < 9; a++) dn[a] = Codec<T>::decode(pf[a], a);
             finish_gather<true>(A, D, xe, yw, m, nb, !A.diag, dn, rRn, rBn,
                                 [&](int a, AT &c, AT &vx, AT &vy) {
                                     const int s2 = (ya - EY[a]) & (Q - 1);
@@ -657,54 +679,74 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
         }
         s_m[sl][lane] = (uint16_t)m;
         s_rn[sl][lane] = rn;
-        s_wx[sl][lane] = pwx;
-        s_wy[sl][lane] = pwy;
+        s_wx[sl][lane] = p.wx;
+        s_wy[sl][lane] = p.wy;
         replicate(s_rn, sl);
+        const bool wall = __builtin_amdgcn_ballot_w64((m & SOLID_BND) != 0) != 0;
+        if (lane % TILE_LANES == 0) s_wall[sl][lane / TILE_LANES] = wall;
+    };
+    // Stages B and D change only outermost solid nodes; an iteration whose B (or D) rows have
+    // none skips that stage and its barrier.  Every wavefront reads the same flags after a
+    // barrier, so the whole block takes the same branch.
+    auto any_wall = [&](int ya) {
+        int f = 0;
+#pragma unroll
+        for (int y = 0; y < R; y++)
+#pragma unroll
+            for (int k = 0; k < C; k++) f |= s_wall[(ya + y) & (Q - 1)][k];
+        return __builtin_amdgcn_readfirstlane(f) != 0;
     };
 
     // prologue: colour rows r_first + R - 1 .. r_first + 2R, stage A of rows r_first + R + w
     load_mask(r_first + R + w);
     if (w < 2) {
-        load_colour(r_first + R - 1 + w);
-        const int sl = (r_first + R - 1 + w) & (Q - 1);
-        s_c[sl][lane] = pc;
-        s_vx[sl][lane] = pvx;
-        s_vy[sl][lane] = pvy;
+        load_colour(r_first + R - 1 + w, cset[0]);
+        put_colour(r_first + R - 1 + w, cset[0]);
     }
-    load_colour(r_first + R + 1 + w);
-    prefetch(r_first + R + w);
-    put_colour(r_first + R + 1 + w);
+    load_colour(r_first + R + 1 + w, cset[0]);
+    prefetch(r_first + R + w, pre);
+    put_colour(r_first + R + 1 + w, cset[0]);
     __syncthreads();
-    stage_a(r_first + R + w);
-    load_colour(r_first + 2 * R + 1 + w);
-    // as many (dropped) stores after the colour loads as the loop issues there, so that the
-    // wait in the first stage D is the same as in every later one
+    stage_a(r_first + R + w, pre);
+    // the colour rows of the first iteration's stage D and the first prefetch, with as many
+    // (dropped) stores in between as the loop issues there, so that the waits in the first
+    // iteration are the same as in every later one
+    load_colour(r_first + 2 * R + 1 + w, cset[1]);
     store_row(NOWHERE, NOWHERE, d, rR, rB, rN);
-    prefetch(r_first + 2 * R + w);
+    prefetch(r_first + 2 * R + w, pre);
 
-    for (int r = r_first; r < y1; r += R) {
+    // One iteration; par selects the colour register sets.
+    auto iteration = [&](int r_, auto par_) __attribute__((always_inline)) {
+        constexpr int par = decltype(par_)::value;
+        // opaque to the compiler's induction analysis: with the loop stepping 2R over rings of
+        // 2R rows every ring slot would look loop-invariant and be hoisted into registers
+        const int r = __builtin_amdgcn_readfirstlane(r_);
+        load_colour(r + 3 * R + 1 + w, cset[par]);  // for the next iteration's stage D
         __syncthreads();
-        // ---- B: virtual colour indicator on outermost solid nodes (Eq. 29)
-        {
-            const int yb = r + R - 1 + w;
-            const int sl = yb & (Q - 1);
-            if (lane >= 2 && lane < TL - 2 && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
-                const uint32_t m = s_m[sl][lane];
-                if (m & SOLID_BND) {
-                    AT num = AT(0), den = AT(0);
-#pragma unroll
-                    for (int a = 1; a < 9; a++) {
-                        if (m & (1u << (a - 1))) continue;
-                        const AT wa = wgt<AT>(a);
-                        num += wa * s_rn[(yb + EY[a]) & (Q - 1)][lanes_of[EX[a] + 1]];
-                        den += wa;
+        const bool do_b = any_wall(r + R - 1), do_d = any_wall(r + R - 3);
+        if (do_b) {
+            // ---- B: virtual colour indicator on outermost solid nodes (Eq. 29)
+            {
+                const int yb = r + R - 1 + w;
+                const int sl = yb & (Q - 1);
+                if (lane >= 2 && lane < TL - 2 && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
+                    const uint32_t m = s_m[sl][lane];
+                    if (m & SOLID_BND) {
+                        AT num = AT(0), den = AT(0);
+    #pragma unroll
+                        for (int a = 1; a < 9; a++) {
+                            if (m & (1u << (a - 1))) continue;
+                            const AT wa = wgt<AT>(a);
+                            num += wa * s_rn[(yb + EY[a]) & (Q - 1)][lanes_of[EX[a] + 1]];
+                            den += wa;
+                        }
+                        s_rn[sl][lane] = num * rcp(den);
                     }
-                    s_rn[sl][lane] = num * rcp(den);
                 }
+                replicate(s_rn, sl);
             }
-            replicate(s_rn, sl);
+            __syncthreads();
         }
-        __syncthreads();
         // ---- C: colour gradient (Eq. 28), wetting correction, interface normal (Eq. 22)
         {
             const int yc = r + R - 2 + w;
@@ -737,35 +779,37 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
             replicate(s_nx, sl);
             replicate(s_ny, sl);
         }
-        __syncthreads();
-        // ---- D: virtual interface normals on outermost solid nodes (Eq. 29, second BC)
-        {
-            const int yd = r + R - 3 + w;
-            const int sl = yd & (Q - 1);
-            if (lane >= 4 && lane < TL - 4 && yd >= y0 - 1 && yd < y1 + 1) {
-                const uint32_t m = s_m[sl][lane];
-                if (m & SOLID_BND) {
-                    AT numx = AT(0), numy = AT(0), den = AT(0);
-#pragma unroll
-                    for (int a = 1; a < 9; a++) {
-                        if (m & (1u << (a - 1))) continue;
-                        const AT wa = wgt<AT>(a);
-                        const int s2 = (yd + EY[a]) & (Q - 1);
-                        const int l2 = lanes_of[EX[a] + 1];
-                        numx += wa * s_nx[s2][l2];
-                        numy += wa * s_ny[s2][l2];
-                        den += wa;
+        if (do_d) {
+            __syncthreads();
+            // ---- D: virtual interface normals on outermost solid nodes (Eq. 29, second BC)
+            {
+                const int yd = r + R - 3 + w;
+                const int sl = yd & (Q - 1);
+                if (lane >= 4 && lane < TL - 4 && yd >= y0 - 1 && yd < y1 + 1) {
+                    const uint32_t m = s_m[sl][lane];
+                    if (m & SOLID_BND) {
+                        AT numx = AT(0), numy = AT(0), den = AT(0);
+    #pragma unroll
+                        for (int a = 1; a < 9; a++) {
+                            if (m & (1u << (a - 1))) continue;
+                            const AT wa = wgt<AT>(a);
+                            const int s2 = (yd + EY[a]) & (Q - 1);
+                            const int l2 = lanes_of[EX[a] + 1];
+                            numx += wa * s_nx[s2][l2];
+                            numy += wa * s_ny[s2][l2];
+                            den += wa;
+                        }
+                        const AT iden = rcp(den);
+                        s_nx[sl][lane] = numx * iden;
+                        s_ny[sl][lane] = numy * iden;
                     }
-                    const AT iden = rcp(den);
-                    s_nx[sl][lane] = numx * iden;
-                    s_ny[sl][lane] = numy * iden;
                 }
+                replicate(s_nx, sl);
+                replicate(s_ny, sl);
             }
-            replicate(s_nx, sl);
-            replicate(s_ny, sl);
-            // colour row for the coming stage A (loads issued in the last stage E)
-            put_colour(r + 2 * R + 1 + w);
         }
+        // colour row for the coming stage A (loaded at the top of the last iteration)
+        put_colour(r + 2 * R + 1 + w, cset[1 - par]);
         __syncthreads();
         // ---- E: curvature (Eq. 13), force (Eq. 10), collision, recolouring state (Eq. 14)
         {
@@ -816,7 +860,6 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
                 vc = nd * CB;
                 if (!isfinite(rho + ux + uy)) atomicOr(A.flag, 1);  // any NaN or overflow
             }
-            load_colour(r + 3 * R + 1 + w);  // for the next stage D; see prefetch
             store_row(vf, vc, o, c, bx, by);
             if (A.diag) {
                 Buf<AT>::store(u_out, vc, 0, ux);
@@ -832,8 +875,18 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
         // r + 2R .. r + 3R - 1, which alias rows r .. r + R - 1; of those, stage E reads only
         // s_m of its own row, written by its own wavefront.  The colour rows it reads were
         // written in stage D, before the last barrier.
-        stage_a(r + 2 * R + w);
-        prefetch(r + 3 * R + w);
+        stage_a(r + 2 * R + w, pre);
+        prefetch(r + 3 * R + w, pre);
+    };
+    // Both exits test the row bound themselves: an exit merged into a shared loop test would
+    // put a path from the first half back to the loop head, where the compiler would then take
+    // the first half's prefetch as possibly still in flight.
+    if (r_first >= y1) return;
+    for (int r = r_first;; r += 2 * R) {
+        iteration(r, std::integral_constant<int, 0>());
+        if (r + R >= y1) break;
+        iteration(r + R, std::integral_constant<int, 1>());
+        if (r + 2 * R >= y1) break;
     }
 }
 
