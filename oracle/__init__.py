@@ -36,7 +36,7 @@ class OrcParams(C.Structure):
         ("beta", C.c_double), ("theta_deg", C.c_double), ("s_e", C.c_double),
         ("s_eps", C.c_double), ("s_q", C.c_double), ("rho0", C.c_double),
         ("eps", C.c_double), ("outlet_u", C.c_double), ("body_fx", C.c_double),
-        ("body_fy", C.c_double),
+        ("body_fy", C.c_double), ("surface_energy", C.c_int32),
     ]
 
 
@@ -81,6 +81,7 @@ def lib():
         L.orc_recolor.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                   C.c_double, dp, dp]
         L.orc_wet_correct.argtypes = [C.c_double] * 6 + [dp]
+        L.orc_grad48.argtypes = [dp, u8p, dp]
         L.orc_e8_table.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int), dp]
         L.orc_e8_normal.argtypes = [u8p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp]
         L.orc_matrices.argtypes = [dp, dp]
@@ -99,13 +100,16 @@ def _u8(a):
     return a.ctypes.data_as(C.POINTER(C.c_uint8))
 
 
-def make_params(nx, ny, open_x=False, scheme=0, **kw) -> OrcParams:
+def make_params(nx, ny, open_x=False, scheme=0, surface_energy=False, **kw) -> OrcParams:
+    """``scheme`` 0 / 1: scheme (a) / (b) of Sec. III A 2; ``surface_energy``: rho^N = cos(theta)
+    on outermost solid nodes without the gradient correction (Sec. III A 1)."""
     d = dict(DEFAULTS)
     unknown = set(kw) - set(d)
     if unknown:
         raise TypeError(f"unknown oracle parameters {sorted(unknown)}")
     d.update(kw)
-    return OrcParams(nx=nx, ny=ny, open_x=int(bool(open_x)), scheme=scheme, **d)
+    return OrcParams(nx=nx, ny=ny, open_x=int(bool(open_x)), scheme=scheme,
+                     surface_energy=int(bool(surface_energy)), **d)
 
 
 class Oracle:
@@ -114,11 +118,11 @@ class Oracle:
     ``inlet_ux`` (ny,) for an open x axis."""
 
     def __init__(self, solid, rho_r0, rho_b0, *, open_x=False, ns=None, inlet_ux=None,
-                 scheme=0, **params):
+                 scheme=0, surface_energy=False, **params):
         L = lib()
         self.solid = np.ascontiguousarray(solid, dtype=np.uint8)
         self.ny, self.nx = self.solid.shape
-        self.params = make_params(self.nx, self.ny, open_x, scheme, **params)
+        self.params = make_params(self.nx, self.ny, open_x, scheme, surface_energy, **params)
         rr = np.ascontiguousarray(rho_r0, dtype=np.float64)
         rb = np.ascontiguousarray(rho_b0, dtype=np.float64)
         nsa = None if ns is None else np.ascontiguousarray(ns, dtype=np.float64)
@@ -225,6 +229,17 @@ def recolor(fp, rR, rB, nx, ny, beta=0.7):
 def wet_correct(ns, g, theta_deg, eps=1e-10):
     out = np.empty(2)
     lib().orc_wet_correct(ns[0], ns[1], theta_deg, eps, g[0], g[1], _dp(out))
+    return out
+
+
+def grad48(phi9, fluid9):
+    """Eq. 48 at one node: phi9[a] = phi(x + e_a) (phi9[0] = phi(x)), fluid9[a] truthy where
+    that neighbour is fluid."""
+    phi = np.ascontiguousarray(phi9, dtype=np.float64)
+    fl = np.ascontiguousarray(np.asarray(fluid9, dtype=bool), dtype=np.uint8)
+    assert phi.shape == (9,) and fl.shape == (9,)
+    out = np.empty(2)
+    lib().orc_grad48(_dp(phi), _u8(fl), _dp(out))
     return out
 
 

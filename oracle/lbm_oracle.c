@@ -19,6 +19,16 @@
  *   -> streaming with half-way bounce-back (Eq. 15) -> open-boundary completion.
  * Each pass reads only arrays completed by earlier passes.
  *
+ * Two per-lattice options give the wetting variants the paper compares (Sec. III A):
+ *  - scheme (b) of Sec. III A 2: no virtual normals on outermost solid nodes; the
+ *    normal derivatives on outermost fluid nodes come from the one-sided mean of
+ *    Eq. 48 over the directions whose neighbour is fluid (Eq. 28 everywhere else);
+ *  - the surface-energy rule of Sec. III A 1: the virtual rho^N on outermost solid
+ *    nodes is cos(theta) instead of Eq. 29, and the colour gradient is not corrected
+ *    (no Eqs. 30-36).
+ * They are independent; the surface-energy model of the comparison in Fig. 2 has no
+ * zero-interface-force condition, i.e. it is the surface-energy rule with scheme (b).
+ *
  * Readings of passages that are garbled or silent (each is listed in the design notes):
  *  - Eq. 3, last row: printed as 0 0 0 0 0 1 1 1 -1, which is not orthogonal to the
  *    others; the p_xy = e_x e_y row 0 0 0 0 0 1 -1 1 -1 is used.
@@ -30,6 +40,8 @@
  *  - The wall normal points into the solid; Eq. 34 is a counter-clockwise rotation by
  *    +theta for (n_f)_1 and by -theta for (n_f)_2; a tie D1 == D2 picks (n_f)_1.
  *  - "Outermost" nodes use the D2Q9 8-neighbourhood; Eq. 29 sums over alpha = 1..8.
+ *  - Eq. 48: alpha_1 runs over 1..8 with a fluid neighbour (the rest direction is in
+ *    neither sum), and the e_{alpha i} of its numerator is read as e_{alpha_1 i}.
  *  - Stencils wrap periodically in y always, in x when x is periodic; with an open x
  *    axis, stencil accesses beyond x = 0 or x = nx-1 are clamped to the edge column, and
  *    the eighth-order wall-normal stencil counts nodes beyond an open edge as fluid.
@@ -50,7 +62,8 @@
 typedef struct {
     int32_t nx, ny;     /* lattice extent including solid nodes */
     int32_t open_x;     /* 0: periodic in x; 1: inlet at x = 0, outlet at x = nx-1 */
-    int32_t scheme;     /* 0: scheme (a) of Sec. III A 2 (virtual normals, Eq. 29) */
+    int32_t scheme;     /* 0: scheme (a) of Sec. III A 2 (virtual normals, Eq. 29);
+                           1: scheme (b) (Eq. 48 on outermost fluid nodes) */
     double nu_r, nu_b;  /* kinematic viscosities of red and blue */
     double sigma;       /* interfacial tension coefficient (Eq. 10) */
     double beta;        /* segregation parameter (Eq. 14) */
@@ -60,6 +73,8 @@ typedef struct {
     double eps;         /* |grad rho^N| threshold below which n = 0 */
     double outlet_u;    /* convective velocity of the outlet condition */
     double body_fx, body_fy; /* uniform body force added to F; a test hook, zero in the paper */
+    int32_t surface_energy;  /* 0: Eq. 29 and Eqs. 30-36; 1: rho^N = cos(theta) on outermost
+                                solid nodes, uncorrected gradient (Sec. III A 1) */
 } orc_params;
 
 /* D2Q9 velocities in the paper's numbering (Sec. II A, after Eq. 7). */
@@ -255,6 +270,22 @@ void orc_wet_correct(double nsx, double nsy, double theta_deg, double eps, doubl
     }
 }
 
+/* Eq. 48: one-sided gradient at an outermost fluid node.  phi9[a] is phi at x + e_a
+ * (phi9[0] = phi(x)), fluid9[a] says whether that neighbour is fluid; the sums run over the
+ * directions a = 1..8 into fluid. */
+void orc_grad48(const double *phi9, const uint8_t *fluid9, double *out) {
+    double sx = 0.0, sy = 0.0, den = 0.0;
+    for (int a = 1; a < 9; a++) {
+        if (!fluid9[a]) continue;
+        double diff = phi9[a] - phi9[0];
+        sx += W[a] * diff * EX[a];
+        sy += W[a] * diff * EY[a];
+        den += W[a];
+    }
+    out[0] = sx / den;
+    out[1] = sy / den;
+}
+
 /* Eighth-order isotropic stencil of Eqs. 32-33: 24 vectors and weights. */
 static int e8_cx[24], e8_cy[24];
 static double e8_w[24];
@@ -336,6 +367,8 @@ void orc_destroy(orc_ctx *c) {
 orc_ctx *orc_create(const orc_params *p, const uint8_t *solid, const double *ns,
                     const double *inlet_ux, const double *rho_r0, const double *rho_b0) {
     if (p->nx < 1 || p->ny < 1 || (p->open_x && p->nx < 2)) return NULL;
+    if ((p->scheme != 0 && p->scheme != 1) || (p->surface_energy != 0 && p->surface_energy != 1))
+        return NULL;
     orc_ctx *c = (orc_ctx *)calloc(1, sizeof(orc_ctx));
     c->p = *p;
     c->nx = p->nx;
@@ -438,6 +471,14 @@ static void pass_virtual(orc_ctx *c, double *phi) {
         }
 }
 
+/* Surface-energy rule: rho^N = cos(theta) on the outermost solid nodes. */
+static void pass_surface_energy(orc_ctx *c) {
+    double v = cos(c->p.theta_deg * M_PI / 180.0);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < (long)c->nn; i++)
+        if (c->cls[i] == CLS_SOLID_BND) c->rhoN[i] = v;
+}
+
 /* Eq. 28 at fluid node (x, y) of field phi (solid neighbours hold virtual values). */
 static void iso_gradient(const orc_ctx *c, const double *phi, int x, int y, double *gx,
                          double *gy) {
@@ -491,9 +532,29 @@ static void pass_normals(orc_ctx *c) {
             c->nvx[i] = c->nvy[i] = 0.0;
         }
     }
-    /* Second boundary condition: virtual normals on outermost solid nodes (Eq. 29). */
-    pass_virtual(c, c->nvx);
-    pass_virtual(c, c->nvy);
+    /* Second boundary condition of scheme (a): virtual normals on outermost solid nodes
+     * (Eq. 29).  Scheme (b) leaves them 0; no stencil reads them then. */
+    if (c->p.scheme == 0) {
+        pass_virtual(c, c->nvx);
+        pass_virtual(c, c->nvy);
+    }
+}
+
+/* Eq. 48 at outermost fluid node (x, y) of field phi. */
+static void one_sided_gradient(const orc_ctx *c, const double *phi, int x, int y, double *gx,
+                               double *gy) {
+    double phi9[9], out[2];
+    uint8_t fluid9[9];
+    phi9[0] = phi[(size_t)y * c->nx + x];
+    fluid9[0] = 1;
+    for (int a = 1; a < 9; a++) {
+        size_t j = nb_index(c, x, y, a);
+        phi9[a] = phi[j];
+        fluid9[a] = !c->solid[j];
+    }
+    orc_grad48(phi9, fluid9, out);
+    *gx = out[0];
+    *gy = out[1];
 }
 
 /* Curvature (Eq. 13), CSF force (Eq. 10) and force-corrected velocity (Eq. 17). */
@@ -508,8 +569,13 @@ static void pass_force(orc_ctx *c) {
                 continue;
             }
             double dnxdx, dnxdy, dnydx, dnydy;
-            iso_gradient(c, c->nvx, x, y, &dnxdx, &dnxdy);
-            iso_gradient(c, c->nvy, x, y, &dnydx, &dnydy);
+            if (c->p.scheme == 1 && c->cls[i] == CLS_FLUID_BND) {
+                one_sided_gradient(c, c->nvx, x, y, &dnxdx, &dnxdy);
+                one_sided_gradient(c, c->nvy, x, y, &dnydx, &dnydy);
+            } else {
+                iso_gradient(c, c->nvx, x, y, &dnxdx, &dnxdy);
+                iso_gradient(c, c->nvy, x, y, &dnydx, &dnydy);
+            }
             double nx = c->nvx[i], ny = c->nvy[i];
             double kappa = -nx * nx * dnydy - ny * ny * dnxdx + nx * ny * (dnxdy + dnydx);
             double Fx = 0.5 * c->p.sigma * kappa * c->gx[i] + c->p.body_fx;
@@ -534,9 +600,12 @@ static void pass_force(orc_ctx *c) {
  * current populations in the context. */
 static void prepare(orc_ctx *c) {
     pass_density(c);
-    pass_virtual(c, c->rhoN);
+    if (c->p.surface_energy)
+        pass_surface_energy(c);
+    else
+        pass_virtual(c, c->rhoN);
     pass_gradient(c);
-    pass_wetting(c);
+    if (!c->p.surface_energy) pass_wetting(c);
     pass_normals(c);
     pass_force(c);
 }
