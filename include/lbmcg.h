@@ -60,11 +60,24 @@ typedef enum {
     LBM_STORE_C16 = 3
 } lbm_storage;
 
+/* Wetting variants of Sec. III A (flags of lbm_domain_desc.wetting; 0 is the paper's model:
+ * virtual rho^N and virtual normals on outermost solid nodes by Eq. 29, the colour gradient
+ * on outermost fluid nodes corrected by Eqs. 30-36).
+ *  LBM_WET_SCHEME_B: scheme (b) of Sec. III A 2.  No virtual normals; on outermost fluid nodes
+ *    the derivatives of n in the curvature (Eq. 13) come from the one-sided mean of Eq. 48
+ *    over the directions whose neighbour is fluid.
+ *  LBM_WET_SURFACE_ENERGY: the surface-energy rule of Sec. III A 1.  The virtual rho^N on
+ *    outermost solid nodes is cos(theta) instead of Eq. 29, and the gradient is not corrected.
+ * The flags combine; the surface-energy model compared in Fig. 2, which has no
+ * zero-interface-force condition, is both together. */
+#define LBM_WET_SCHEME_B 1
+#define LBM_WET_SURFACE_ENERGY 2
+
 /* One domain.  Host pointers are read during lbm_create only. */
 typedef struct {
     int32_t nx, ny;           /* lattice extent including solid nodes; nx >= 2 if open_x */
     int32_t open_x;           /* 0: periodic x; 1: velocity inlet at x = 0, outlet at nx-1 */
-    int32_t reserved;         /* must be 0 */
+    int32_t wetting;          /* LBM_WET_* flags (0: the paper's model); other bits invalid */
     const uint8_t *solid;     /* nx*ny, nonzero = solid (required) */
     const double *ns;         /* optional nx*ny*2 wall normal pointing into the solid,
                                  used on outermost fluid nodes; NULL = eighth-order stencil */

@@ -16,6 +16,9 @@
 
 using namespace lbmcg;
 
+static_assert(WET_SCHEME_B == LBM_WET_SCHEME_B && WET_SURFACE_ENERGY == LBM_WET_SURFACE_ENERGY,
+              "device wetting flags follow the interface's");
+
 namespace {
 
 thread_local std::string g_err;
@@ -123,7 +126,8 @@ int validate(const lbm_domain_desc *d, int n, int storage) {
         if (q.nx < 1 || q.ny < 1) return fail(LBM_EINVAL, "domain %d: bad extent %dx%d", i, q.nx, q.ny);
         if ((long long)q.nx * q.ny > (1LL << 31)) return fail(LBM_EINVAL, "domain %d too large", i);
         if (q.open_x && q.nx < 2) return fail(LBM_EINVAL, "domain %d: open x needs nx >= 2", i);
-        if (q.reserved != 0) return fail(LBM_EINVAL, "domain %d: reserved field must be 0", i);
+        if (q.wetting & ~(LBM_WET_SCHEME_B | LBM_WET_SURFACE_ENERGY))
+            return fail(LBM_EINVAL, "domain %d: unknown wetting flags 0x%x", i, (unsigned)q.wetting);
         if (!q.solid || !q.rho_r0 || !q.rho_b0) return fail(LBM_EINVAL, "domain %d: missing array", i);
         if (q.open_x && !q.inlet_ux) return fail(LBM_EINVAL, "domain %d: open x needs inlet_ux", i);
         if (!(q.nu_r > 0) || !(q.nu_b > 0)) return fail(LBM_EINVAL, "domain %d: viscosity must be > 0 (tau > 1/2)", i);
@@ -251,6 +255,7 @@ struct lbm_ctx {
     int chunk_rows = 0;
     int waves = 0;    // wavefronts (tile rows advanced per iteration) of the step kernel
     int cols = 1;     // wavefronts side by side in a tile row (tile width 64 cols)
+    bool variants = false;  // some domain uses a wetting variant (LBM_WET_*)
     int parity = 0;   // buffer holding the current state
     int own = 1;      // current state is a node-local snapshot
     int64_t steps = 0;
@@ -429,6 +434,7 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
         D.nx = q.nx;
         D.ny = q.ny;
         D.open_x = q.open_x ? 1 : 0;
+        D.wetting = q.wetting;
         D.io_off = io;
         DomPar<double> &PD = D.d;
         PD.inv2nu_r = 1.0 / (2.0 * q.nu_r);
@@ -533,6 +539,7 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     lbm_ctx *c = new lbm_ctx();
     c->n = n;
     c->storage = storage;
+    for (int i = 0; i < n; i++) c->variants = c->variants || domains[i].wetting != 0;
     c->stream = (hipStream_t)hip_stream;
     c->state = (char *)state_dev;
     c->scratch = (char *)scratch_dev;
@@ -584,7 +591,7 @@ int lbm_step(lbm_ctx *c, int64_t n_steps) {
     if (n_steps < 0) return fail(LBM_EINVAL, "negative step count");
     for (int64_t k = 0; k < n_steps; k++) {
         AnyArgs a = make_args(c, c->parity);
-        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->cols, c->stream));
+        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
         c->parity ^= 1;
         c->own = 0;
         c->steps++;
@@ -613,7 +620,7 @@ int lbm_read_fields(lbm_ctx *c, int domain, uint32_t which, double *out_dev, siz
     }
     if (which & 24u) {
         AnyArgs da = make_diag_args(c);
-        HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->stream));
+        HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
         double *ox = (which & 8u) ? out_dev + (p++) * nn : nullptr;
         double *oy = (which & 16u) ? out_dev + p * nn : nullptr;
         HIP_OK(launch_velocity_copy(c->storage, a.bytes, domain, c->diag + diag_layout(c).u, ox, oy,
@@ -714,7 +721,7 @@ int lbm_diag_velocity(lbm_ctx *c, int snapshot, double *out_host) {
     if (!c->diag) return fail(LBM_ESTATE, "no diagnostics buffer attached (lbm_diag_attach)");
     const DiagLayout DL = diag_layout(c);
     AnyArgs da = make_diag_args(c);
-    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->stream));
+    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
     double *res = reinterpret_cast<double *>(c->diag + DL.res);
     HIP_OK(launch_velocity_stats(c->storage, da.bytes, c->n, c->diag + DL.u,
                                  c->snap_valid ? c->diag + DL.snap : nullptr,

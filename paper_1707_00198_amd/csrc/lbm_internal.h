@@ -29,10 +29,14 @@ struct DomPar {
     AT s_e, s_eps, s_q, ke, keps, kq, outlet_u, pad;
 };
 
+// Wetting variants (same values as the LBM_WET_* flags of the interface).
+constexpr int WET_SCHEME_B = 1;         // Eq. 48 for grad n on outermost fluid nodes
+constexpr int WET_SURFACE_ENERGY = 2;   // rho^N = cos(theta) on outermost solid nodes
+
 struct DomDev {
     long long off;       // first node of the domain in every node plane
     int nx, ny;
-    int open_x, pad0;
+    int open_x, wetting;
     long long io_off;    // first row of the domain in the inlet / outlet row arrays
     DomPar<double> d;    // parameters for FP64 arithmetic
     DomPar<float> f;     // the same, rounded once, for FP32 arithmetic
@@ -86,8 +90,10 @@ struct StepArgs {
 };
 
 // Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16, 3 c16.
-// waves x cols wavefronts per block: (4, 1), (8, 1) or (4, 2); a tile is 64 cols columns wide
-hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols, hipStream_t s);
+// waves x cols wavefronts per block: (4, 1), (8, 1) or (4, 2); a tile is 64 cols columns wide.
+// variants: some domain has nonzero wetting flags (selects the kernel that tests them).
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols,
+                       bool variants, hipStream_t s);
 hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, uint32_t which,
                        double *out, hipStream_t s);
 hipError_t launch_mass(int storage, const void *args, int n_doms, const int *dom_nodes_begin,

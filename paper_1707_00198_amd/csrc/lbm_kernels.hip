@@ -506,8 +506,9 @@ struct Buf<uint16_t> {
 // rows r + R - 1 + w, r + R - 2 + w, r + R - 3 + w and r + w (w = wavefront), then stage A of
 // the next iteration's rows r + 2R + w, and issues the loads for the stage A after that.  Stage E
 // of a row runs on the thread that gathered the row one iteration earlier.  LDS rings hold 2R
-// rows.
-template <class T, int R, int C>
+// rows.  WV: some domain of the launch uses a wetting variant (Sec. III A); without it the
+// variant branches are compiled out.
+template <class T, int R, int C, bool WV>
 __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 4 ? 4 : 2) void step_kernel(const StepArgs<T, typename Codec<T>::AT> A) {
     using AT = typename Codec<T>::AT;
     constexpr int Q = 2 * R;
@@ -547,6 +548,8 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     const bool gather_lane = lane >= 1 && lane < TL - 1;
     ParC<AT> &P = par(D, AT());
     const AT eps = P.eps;
+    const bool scheme_b = WV && (D.wetting & WET_SCHEME_B);
+    const bool surface_energy = WV && (D.wetting & WET_SURFACE_ENERGY);
     const int r_first = y0 - HALO + 1 - R;  // first stage A row is y0 - 4
 
     // a diagnostic launch writes no state (zero extents drop every store) but the velocity
@@ -723,7 +726,8 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
         const int r = __builtin_amdgcn_readfirstlane(r_);
         load_colour(r + 3 * R + 1 + w, cset[par]);  // for the next iteration's stage D
         __syncthreads();
-        const bool do_b = any_wall(r + R - 1), do_d = any_wall(r + R - 3);
+        // scheme (b) has no virtual normals: stage D is skipped on every row
+        const bool do_b = any_wall(r + R - 1), do_d = !scheme_b && any_wall(r + R - 3);
         if (do_b) {
             // ---- B: virtual colour indicator on outermost solid nodes (Eq. 29)
             {
@@ -731,7 +735,9 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
                 const int sl = yb & (Q - 1);
                 if (lane >= 2 && lane < TL - 2 && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
                     const uint32_t m = s_m[sl][lane];
-                    if (m & SOLID_BND) {
+                    if ((m & SOLID_BND) && surface_energy) {
+                        s_rn[sl][lane] = P.cos_t;  // surface-energy rule
+                    } else if (m & SOLID_BND) {
                         AT num = AT(0), den = AT(0);
     #pragma unroll
                         for (int a = 1; a < 9; a++) {
@@ -766,7 +772,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
                         gx = AT(3) * sx;
                         gy = AT(3) * sy;
                     }
-                    if (m & FLUID_BND)
+                    if ((m & FLUID_BND) && !surface_energy)
                         wetting_correct(s_wx[sl][lane], s_wy[sl][lane], P.cos_t, P.sin_t, eps, gx, gy);
                     const AT g = fsqrt(gx * gx + gy * gy);
                     if (g > eps) unit_normal(gx, gy, g, nx, ny);
@@ -821,9 +827,35 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
 #pragma unroll
             for (int a = 0; a < 9; a++) o[a] = d[a];
             uint32_t vf = NOWHERE, vc = NOWHERE;
-            if (out_lane && ye >= y0 && ye < y1 && !(s_m[sl][lane] & SELF_SOLID)) {
+            const uint32_t me = s_m[sl][lane];
+            if (out_lane && ye >= y0 && ye < y1 && !(me & SELF_SOLID)) {
                 AT dxnx = AT(0), dynx = AT(0), dxny = AT(0), dyny = AT(0);
-                {
+                if (scheme_b && (me & FLUID_BND)) {
+                    // Eq. 48: weighted mean of the differences to the fluid neighbours
+                    const AT nx0 = s_nx[sl][lane], ny0 = s_ny[sl][lane];
+                    AT den = AT(0);
+#pragma unroll
+                    for (int a = 1; a < 9; a++) {
+                        if (me & (1u << (a - 1))) continue;
+                        const int s2 = (ye + EY[a]) & (Q - 1);
+                        const int l2 = lanes_of[EX[a] + 1];
+                        const AT vx = s_nx[s2][l2] - nx0, vy = s_ny[s2][l2] - ny0;
+                        if (EX[a]) {
+                            dxnx += wgt<AT>(a) * vx * AT(EX[a]);
+                            dxny += wgt<AT>(a) * vy * AT(EX[a]);
+                        }
+                        if (EY[a]) {
+                            dynx += wgt<AT>(a) * vx * AT(EY[a]);
+                            dyny += wgt<AT>(a) * vy * AT(EY[a]);
+                        }
+                        den += wgt<AT>(a);
+                    }
+                    const AT iden = rcp(den);
+                    dxnx *= iden;
+                    dynx *= iden;
+                    dxny *= iden;
+                    dyny *= iden;
+                } else {
 #pragma unroll
                     for (int a = 1; a < 9; a++) {
                         const int s2 = (ye + EY[a]) & (Q - 1);
@@ -1161,25 +1193,33 @@ __global__ __launch_bounds__(DIAG_THREADS) void crossing_kernel(
 }
 
 // ------------------------------------------------------------------- launchers
-template <class T>
+template <class T, bool WV>
 static hipError_t step_t(const void *args, int n_items, int waves, int cols, hipStream_t s) {
     const auto &A = *static_cast<const StepArgs<T, typename Codec<T>::AT> *>(args);
     if (cols == 2)
-        hipLaunchKernelGGL((step_kernel<T, 4, 2>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
+        hipLaunchKernelGGL((step_kernel<T, 4, 2, WV>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
     else if (waves == 8)
-        hipLaunchKernelGGL((step_kernel<T, 8, 1>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
+        hipLaunchKernelGGL((step_kernel<T, 8, 1, WV>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
     else
-        hipLaunchKernelGGL((step_kernel<T, 4, 1>), dim3(n_items), dim3(TILE_LANES * 4), 0, s, A);
+        hipLaunchKernelGGL((step_kernel<T, 4, 1, WV>), dim3(n_items), dim3(TILE_LANES * 4), 0, s, A);
     return hipGetLastError();
 }
 
-hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols, hipStream_t s) {
+template <class T>
+static hipError_t step_v(const void *args, int n_items, int waves, int cols, bool variants,
+                         hipStream_t s) {
+    return variants ? step_t<T, true>(args, n_items, waves, cols, s)
+                    : step_t<T, false>(args, n_items, waves, cols, s);
+}
+
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols,
+                       bool variants, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (storage) {
-        case 0: return step_t<double>(args, n_items, waves, cols, s);
-        case 1: return step_t<float>(args, n_items, waves, cols, s);
-        case 2: return step_t<__half>(args, n_items, waves, cols, s);
-        case 3: return step_t<C16>(args, n_items, waves, cols, s);
+        case 0: return step_v<double>(args, n_items, waves, cols, variants, s);
+        case 1: return step_v<float>(args, n_items, waves, cols, variants, s);
+        case 2: return step_v<__half>(args, n_items, waves, cols, variants, s);
+        case 3: return step_v<C16>(args, n_items, waves, cols, variants, s);
     }
     return hipErrorInvalidValue;
 }

@@ -26,9 +26,14 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
 _dp = C.POINTER(C.c_double)
 
 
+# Wetting variants (LBM_WET_* of include/lbmcg.h).
+WET_SCHEME_B = 1
+WET_SURFACE_ENERGY = 2
+
+
 class DomainDesc(C.Structure):
     _fields_ = [
-        ("nx", C.c_int32), ("ny", C.c_int32), ("open_x", C.c_int32), ("reserved", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("open_x", C.c_int32), ("wetting", C.c_int32),
         ("solid", C.POINTER(C.c_uint8)), ("ns", _dp), ("inlet_ux", _dp), ("rho_r0", _dp),
         ("rho_b0", _dp),
         ("nu_r", C.c_double), ("nu_b", C.c_double), ("sigma", C.c_double), ("beta", C.c_double),
@@ -102,7 +107,7 @@ class Lattice:
     """A batch of domains advanced together by the fused HIP step.
 
     ``setups`` are objects with the attributes of ``workloads.Setup`` (solid, rho_r0, rho_b0,
-    params, open_x, inlet_ux, ns).  ``storage`` is 'f64', 'f32', 'f16' or 'c16'.
+    params, open_x, inlet_ux, ns, and optionally wetting: WET_* flags).  ``storage`` is 'f64', 'f32', 'f16' or 'c16'.
     """
 
     def __init__(self, setups: Sequence, storage: str = "f64", device="cuda:0"):
@@ -123,7 +128,7 @@ class Lattice:
             self._keep += [solid, rr, rb]
             d.nx, d.ny = solid.shape[1], solid.shape[0]
             d.open_x = int(bool(s.open_x))
-            d.reserved = 0
+            d.wetting = int(getattr(s, "wetting", 0))
             d.solid = _ptr(solid, C.c_uint8)
             d.rho_r0 = _ptr(rr, C.c_double)
             d.rho_b0 = _ptr(rb, C.c_double)

@@ -19,6 +19,10 @@ import numpy as np
 
 SEED = 170700198
 
+# Wetting variants of a set-up (Sec. III A): scheme (b) of Eq. 48 and the surface-energy rule.
+WET_SCHEME_B = 1
+WET_SURFACE_ENERGY = 2
+
 PHYS_KEYS = ("nu_r", "nu_b", "sigma", "beta", "theta_deg", "s_e", "s_eps", "s_q", "rho0",
              "eps", "outlet_u")
 
@@ -35,6 +39,7 @@ class Setup:
     inlet_ux: Optional[np.ndarray] = None   # (ny,) inlet velocity profile
     ns: Optional[np.ndarray] = None         # (ny, nx, 2) analytic wall normal into the solid
     meta: dict = dataclasses.field(default_factory=dict)
+    wetting: int = 0             # WET_* flags; 0 is the paper's model
 
     @property
     def ny(self):
@@ -49,7 +54,9 @@ class Setup:
         return int((self.solid == 0).sum())
 
     def oracle_kwargs(self):
-        return dict(open_x=self.open_x, ns=self.ns, inlet_ux=self.inlet_ux, **self.params)
+        return dict(open_x=self.open_x, ns=self.ns, inlet_ux=self.inlet_ux,
+                    scheme=1 if self.wetting & WET_SCHEME_B else 0,
+                    surface_energy=bool(self.wetting & WET_SURFACE_ENERGY), **self.params)
 
 
 def _phys(**kw):

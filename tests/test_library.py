@@ -40,6 +40,7 @@ def _desc(s):
     rb = np.ascontiguousarray(s.rho_b0)
     keep += [solid, rr, rb]
     d.nx, d.ny, d.open_x = s.nx, s.ny, int(s.open_x)
+    d.wetting = s.wetting
     d.solid = solid.ctypes.data_as(C.POINTER(C.c_uint8))
     d.rho_r0 = rr.ctypes.data_as(C.POINTER(C.c_double))
     d.rho_b0 = rb.ctypes.data_as(C.POINTER(C.c_double))
@@ -91,6 +92,16 @@ def test_invalid_geometry_is_rejected():
     rc, *_, err = query(s)
     assert rc == -1 and "inlet" in err
     assert query(s, storage=7)[0] == -1
+
+
+def test_wetting_flags_validated():
+    s = W.cfg_droplet_flat()
+    for ok in (W.WET_SCHEME_B, W.WET_SURFACE_ENERGY, W.WET_SCHEME_B | W.WET_SURFACE_ENERGY):
+        s.wetting = ok
+        assert query(s)[0] == 0
+    s.wetting = 4
+    rc, *_, err = query(s)
+    assert rc == -1 and "wetting" in err
 
 
 def test_lattice_refuses_without_gpu():

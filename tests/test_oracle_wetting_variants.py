@@ -69,7 +69,7 @@ def test_surface_energy_gradient_at_pure_red_channel(theta):
     kw = s.oracle_kwargs()
     kw["open_x"] = False
     kw.pop("inlet_ux", None)
-    se = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, surface_energy=True, **kw)
+    se = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **dict(kw, surface_energy=True))
     geo = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **kw)
     gx, gy = se.field("gx"), se.field("gy")
     want = 0.5 * (1.0 - np.cos(np.radians(theta)))
@@ -112,8 +112,8 @@ def test_variants_differ_with_a_contact_line():
     s = W.droplet_flat(nx=80, h=40, radius=15.0, theta_deg=60.0, xc=39.37)
     kw = s.oracle_kwargs()
     ref = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **kw).step(20).pops()
-    b = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, scheme=1, **kw).step(20).pops()
-    se = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, surface_energy=True, **kw).step(20).pops()
+    b = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **dict(kw, scheme=1)).step(20).pops()
+    se = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **dict(kw, surface_energy=True)).step(20).pops()
     assert np.abs(b - ref).max() > 1e-8
     assert np.abs(se - ref).max() > 1e-6
 
@@ -125,7 +125,8 @@ def test_table2_scheme_b_spurious_velocity(k):
     tab = json.load(open(GOLDEN))
     theta = tab["table1_theta_prescribed"][k]
     s = W.droplet_box(theta_deg=theta, M=1.0)
-    o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, scheme=1, **s.oracle_kwargs())
+    s.wetting = W.WET_SCHEME_B
+    o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **s.oracle_kwargs())
     o.step(3000)
     th, _ = physics.flat_contact_angle(o.field("rhoN"), s.solid, 0.5)
     assert abs(th - theta) < 0.5
@@ -152,8 +153,9 @@ def test_fig2_npmt_present_model_versus_surface_energy():
                        rb[fluid & inside].sum(), rb[fluid & ~inside].sum()])
 
     curves = {}
-    for name, kw in (("present", {}), ("surface energy", dict(scheme=1, surface_energy=True))):
-        o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **kw, **s.oracle_kwargs())
+    for name, wet in (("present", 0), ("surface energy", W.WET_SCHEME_B | W.WET_SURFACE_ENERGY)):
+        s.wetting = wet
+        o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **s.oracle_kwargs())
         curves[name] = [npmt(o.step(1000)), npmt(o.step(2000))]
     print(curves)
     p, e = curves["present"], curves["surface energy"]
