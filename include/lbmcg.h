@@ -185,6 +185,16 @@ int lbm_diag_region_mass(lbm_ctx *ctx, int domain, const uint8_t *region_dev, do
 int lbm_diag_crossings(lbm_ctx *ctx, int domain, const int32_t *rows_host, int n_rows,
                        double *out_host);
 
+/* The dynamic contact-line list (the part of the outermost fluid nodes where the wetting
+ * condition of Sec. II C acts): the outermost fluid nodes of `domain` whose colour gradient of
+ * the current state (Eq. 28 with the virtual values, before the correction of Eqs. 30-36) has
+ * |grad rho^N| > eps.  Pure-phase wall regions, where the gradient vanishes, are not listed.
+ * Computed on the device by a diagnostic launch (no state is written).  Sets *count to the
+ * number of such nodes and writes their indices y * nx + x in ascending order to out_host
+ * (host array of `cap` entries); LBM_ENOMEM, with *count set and out_host untouched, if
+ * *count > cap.  Needs an attached diagnostics buffer. */
+int lbm_diag_contact_line(lbm_ctx *ctx, int domain, int32_t *out_host, int cap, int *count);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbm_last_error(void);
 

@@ -266,6 +266,7 @@ struct lbm_ctx {
     double *diag_host = nullptr;
     int *rows_host = nullptr;
     bool snap_valid = false;
+    int max_fluid_bnd = 0;  // largest number of outermost fluid nodes in one domain
 };
 
 namespace {
@@ -306,9 +307,11 @@ struct AnyArgs {
 };
 
 // Layout of the diagnostics buffer: velocity (u_x, u_y planes at the colour-plane stride), its
-// snapshot, reduction partials and results, and the row list and results of crossings.
+// snapshot, reduction partials and results, the row list and results of crossings, and the
+// contact-line counter and list (room for every outermost fluid node of the largest domain).
 struct DiagLayout {
-    size_t u = 0, snap = 0, part = 0, res = 0, rows = 0, cross = 0, bytes = 0;
+    size_t u = 0, snap = 0, part = 0, res = 0, rows = 0, cross = 0, cl_count = 0, cl_list = 0,
+           bytes = 0;
 };
 DiagLayout diag_layout(const lbm_ctx *c) {
     DiagLayout D;
@@ -326,14 +329,22 @@ DiagLayout diag_layout(const lbm_ctx *c) {
     o += align_up(DIAG_MAX_ROWS * sizeof(int), 256);
     D.cross = o;
     o += align_up(DIAG_MAX_ROWS * sizeof(double), 256);
+    D.cl_count = o;
+    o += 256;
+    D.cl_list = o;
+    o += align_up(std::max<size_t>((size_t)c->max_fluid_bnd, 1) * sizeof(int32_t), 256);
     D.bytes = o;
     return D;
 }
 
 template <class T, class AT>
-void set_diag_t(StepArgs<T, AT> &A, void *u) {
+void set_diag_t(StepArgs<T, AT> &A, void *u, void *cl_list, void *cl_count, int cl_cap, int cl_dom) {
     A.u_out = static_cast<AT *>(u);
     A.diag = 1;
+    A.cl_list = static_cast<int32_t *>(cl_list);
+    A.cl_count = static_cast<int *>(cl_count);
+    A.cl_cap = cl_cap;
+    A.cl_dom = cl_dom;
 }
 
 AnyArgs make_args(const lbm_ctx *c, int parity) {
@@ -346,14 +357,19 @@ AnyArgs make_args(const lbm_ctx *c, int parity) {
     return a;
 }
 
-// Arguments of a diagnostic launch on the current state: velocity into the diagnostics buffer.
-AnyArgs make_diag_args(const lbm_ctx *c) {
+// Arguments of a diagnostic launch on the current state: velocity into the diagnostics buffer,
+// and, for cl_dom >= 0, the contact-line list of that domain.
+AnyArgs make_diag_args(const lbm_ctx *c, int cl_dom = -1) {
     AnyArgs a = make_args(c, c->parity);
-    void *u = c->diag + diag_layout(c).u;
-    if (c->storage == 0) set_diag_t(*reinterpret_cast<StepArgs<double, double> *>(a.bytes), u);
-    else if (c->storage == 1) set_diag_t(*reinterpret_cast<StepArgs<float, float> *>(a.bytes), u);
-    else if (c->storage == 2) set_diag_t(*reinterpret_cast<StepArgs<__half, float> *>(a.bytes), u);
-    else set_diag_t(*reinterpret_cast<StepArgs<C16, float> *>(a.bytes), u);
+    const DiagLayout DL = diag_layout(c);
+    void *u = c->diag + DL.u;
+    void *list = cl_dom >= 0 ? c->diag + DL.cl_list : nullptr;
+    void *count = cl_dom >= 0 ? c->diag + DL.cl_count : nullptr;
+    const int cap = c->max_fluid_bnd;
+    if (c->storage == 0) set_diag_t(*reinterpret_cast<StepArgs<double, double> *>(a.bytes), u, list, count, cap, cl_dom);
+    else if (c->storage == 1) set_diag_t(*reinterpret_cast<StepArgs<float, float> *>(a.bytes), u, list, count, cap, cl_dom);
+    else if (c->storage == 2) set_diag_t(*reinterpret_cast<StepArgs<__half, float> *>(a.bytes), u, list, count, cap, cl_dom);
+    else set_diag_t(*reinterpret_cast<StepArgs<C16, float> *>(a.bytes), u, list, count, cap, cl_dom);
     return a;
 }
 
@@ -456,12 +472,14 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
         const double *pd = &PD.rho0;
         float *pf = &D.f.rho0;
         for (size_t k = 0; k < sizeof(DomPar<double>) / sizeof(double); k++) pf[k] = (float)pd[k];
+        int n_fluid_bnd = 0;
         for (int y = 0; y < q.ny; y++)
             for (int x = 0; x < q.nx; x++) {
                 const size_t k = (size_t)y * q.nx + x, g = off + k;
                 double vx, vy;
                 const uint32_t m = node_class(q, x, y, vx, vy);
                 const bool s = (m & SELF_SOLID) != 0;
+                n_fluid_bnd += (m & FLUID_BND) ? 1 : 0;
                 mask[g] = (uint16_t)m;
                 nsx[g] = (AT)vx;
                 nsy[g] = (AT)vy;
@@ -476,6 +494,7 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
                     hist[3 * (io + y) + 2] = (AT)(WH[7] * (rho - q.rho0));
                 }
             }
+        c->max_fluid_bnd = std::max(c->max_fluid_bnd, n_fluid_bnd);
         if (q.open_x)
             for (int y = 0; y < q.ny; y++) inlet[io + y] = (AT)q.inlet_ux[y];
         off += (long long)align_up((size_t)q.nx * q.ny, 64);
@@ -773,6 +792,30 @@ int lbm_diag_crossings(lbm_ctx *c, int domain, const int32_t *rows_host, int n_r
     HIP_OK(hipMemcpyAsync(c->diag_host, out, (size_t)n_rows * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     std::memcpy(out_host, c->diag_host, (size_t)n_rows * sizeof(double));
+    return LBM_OK;
+}
+
+int lbm_diag_contact_line(lbm_ctx *c, int domain, int32_t *out_host, int cap, int *count) {
+    if (!c || !count || (cap > 0 && !out_host)) return fail(LBM_EINVAL, "null argument");
+    if (domain < 0 || domain >= c->n) return fail(LBM_EINVAL, "domain %d out of range", domain);
+    if (cap < 0) return fail(LBM_EINVAL, "negative capacity");
+    if (!c->diag) return fail(LBM_ESTATE, "no diagnostics buffer attached (lbm_diag_attach)");
+    const DiagLayout DL = diag_layout(c);
+    int *dcount = reinterpret_cast<int *>(c->diag + DL.cl_count);
+    HIP_OK(hipMemsetAsync(dcount, 0, sizeof(int), c->stream));
+    AnyArgs da = make_diag_args(c, domain);
+    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
+    HIP_OK(hipMemcpyAsync(c->rows_host, dcount, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const int n = c->rows_host[0];
+    *count = n;
+    if (n > c->max_fluid_bnd)  // each node is recorded once: cannot happen
+        return fail(LBM_EDEVICE, "contact-line list overflow (%d entries)", n);
+    if (n > cap) return fail(LBM_ENOMEM, "%d contact-line nodes, room for %d", n, cap);
+    if (n > 0) {
+        HIP_OK(hipMemcpy(out_host, c->diag + DL.cl_list, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::sort(out_host, out_host + n);
+    }
     return LBM_OK;
 }
 

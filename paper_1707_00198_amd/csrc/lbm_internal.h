@@ -87,6 +87,13 @@ struct StepArgs {
     // c_plane_bytes apart.
     AT *u_out;
     int diag;
+    // Contact-line list of a diagnostic launch (cl_count == nullptr: none): every outermost
+    // fluid node of domain cl_dom with |grad rho^N| > eps (before the correction of Eqs. 30-36)
+    // adds one to *cl_count and, while there is room, its index y * nx + x to cl_list (cl_cap
+    // entries, in no particular order).
+    int32_t *cl_list;
+    int *cl_count;
+    int cl_cap, cl_dom;
 };
 
 // Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16, 3 c16.

@@ -548,6 +548,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     const bool gather_lane = lane >= 1 && lane < TL - 1;
     ParC<AT> &P = par(D, AT());
     const AT eps = P.eps;
+    const bool rec_cl = A.diag && A.cl_count != nullptr && dom == A.cl_dom;
     const bool scheme_b = WV && (D.wetting & WET_SCHEME_B);
     const bool surface_energy = WV && (D.wetting & WET_SURFACE_ENERGY);
     const int r_first = y0 - HALO + 1 - R;  // first stage A row is y0 - 4
@@ -771,6 +772,12 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
                         }
                         gx = AT(3) * sx;
                         gy = AT(3) * sy;
+                    }
+                    // contact-line list: each node is recorded by the tile that outputs it
+                    if (rec_cl && (m & FLUID_BND) && out_lane && yc >= y0 && yc < y1 &&
+                        fsqrt(gx * gx + gy * gy) > eps) {
+                        const int k = atomicAdd(A.cl_count, 1);
+                        if (k < A.cl_cap) A.cl_list[k] = yc * D.nx + X;
                     }
                     if ((m & FLUID_BND) && !surface_energy)
                         wetting_correct(s_wx[sl][lane], s_wy[sl][lane], P.cos_t, P.sin_t, eps, gx, gy);

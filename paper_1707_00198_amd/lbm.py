@@ -21,6 +21,7 @@ FIELD_RHO_R, FIELD_RHO_B, FIELD_POPS, FIELD_UX, FIELD_UY = 1, 2, 4, 8, 16
 
 STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE",
           -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 
 # Exported symbols and their prototypes, as declared in include/lbmcg.h.
 _dp = C.POINTER(C.c_double)
@@ -62,6 +63,8 @@ PROTOTYPES = {
     "lbm_diag_velocity": (C.c_int, [C.c_void_p, C.c_int, _dp]),
     "lbm_diag_region_mass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, _dp]),
     "lbm_diag_crossings": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int, _dp]),
+    "lbm_diag_contact_line": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int,
+                                        C.POINTER(C.c_int)]),
     "lbm_last_error": (C.c_char_p, []),
     "lbm_destroy": (None, [C.c_void_p]),
 }
@@ -247,6 +250,25 @@ class Lattice:
         _check(load_library().lbm_diag_crossings(self._h, dom, _ptr(rows, C.c_int32), len(rows),
                                                  _ptr(out, C.c_double)))
         return out
+
+    def contact_line(self, dom: int) -> np.ndarray:
+        """Outermost fluid nodes of domain ``dom`` where |grad rho^N| > eps (the nodes the
+        wetting condition acts on), as an (n, 2) array of (x, y), ordered by y then x."""
+        self._diag()
+        L = load_library()
+        n = C.c_int()
+        cap = 256
+        while True:
+            out = np.empty(cap, dtype=np.int32)
+            rc = L.lbm_diag_contact_line(self._h, dom, _ptr(out, C.c_int32), cap, C.byref(n))
+            if rc == STATUS_CODE["LBM_ENOMEM"] and n.value > cap:
+                cap = n.value
+                continue
+            _check(rc)
+            break
+        nx = self.setups[dom].solid.shape[1]
+        idx = out[:n.value]
+        return np.stack([idx % nx, idx // nx], axis=1)
 
     # -------------------------------------------------------------- checkpoints
     def save_state(self):

@@ -155,3 +155,57 @@ def test_steady_droplet_npmt_and_spurious_velocity():
           flush=True)
     assert 1e-7 <= umax[0] <= 1e-3
     assert e < 0.05
+
+
+def _want_contact_line(s, o):
+    """Outermost fluid nodes where the oracle's colour gradient exceeds eps (|g| is unchanged
+    by the correction of Eqs. 30-36 up to rounding), and |g| / eps for the tie check."""
+    g = np.hypot(o.field("gx"), o.field("gy"))
+    ratio = g / s.params["eps"]
+    return (o.classes() == 1) & (ratio > 1.0), ratio
+
+
+def _contact_line_cases():
+    se = W.fingering_channel(nx=160, h=30, x_interface=50.0, M=5.0, theta_deg=60.0, ca=0.1,
+                             nu_r=0.5, sigma=0.01, name="channel_se")
+    se.wetting = W.WET_SURFACE_ENERGY
+    return _cases() + [
+        W.cylinder_droplet(n=96, rc=20.0, rd=18.0, theta_deg=120.0, ccx=48.0, ccy=30.0,
+                           name="cyl_e8", dcx_offset=0.37), se]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_contact_line_list_matches_oracle(idx):
+    """The device list equals the oracle's set of outermost fluid nodes with |grad rho^N| >
+    eps, node for node (FP64 on both sides; a node within 1 % of the threshold may differ)."""
+    s = _contact_line_cases()[idx]
+    lat = _lattice([s]).step(300)
+    o = _oracle(s).step(300)
+    got = lat.contact_line(0)
+    want, ratio = _want_contact_line(s, o)
+    got_mask = np.zeros_like(want)
+    got_mask[got[:, 1], got[:, 0]] = True
+    assert len(got) == got_mask.sum()  # no node listed twice
+    differ = got_mask != want
+    print(f"[contact line] {s.name}: {len(got)} nodes listed, oracle {want.sum()}, "
+          f"differing {differ.sum()}", flush=True)
+    assert want.sum() > 0
+    assert np.all(np.abs(ratio[differ] - 1.0) < 0.01)
+    assert np.all(o.classes()[got_mask] == 1)
+
+
+def test_contact_line_list_pure_channel_closed_forms():
+    """Pure red channel, initial state: the geometric rule lists nothing (the virtual rho^N of
+    Eq. 29 equals the fluid's); the surface-energy rule at 60 degrees gives every wall node
+    g_y = +-(1 - cos 60) / 2 != 0, so it lists every outermost fluid node."""
+    s = W.fingering_channel(nx=100, h=20, x_interface=1e9, M=1.0, theta_deg=60.0, ca=0.1,
+                            nu_r=0.1, sigma=0.01, name="pure")
+    se = W.fingering_channel(nx=100, h=20, x_interface=1e9, M=1.0, theta_deg=60.0, ca=0.1,
+                             nu_r=0.1, sigma=0.01, name="pure_se")
+    se.wetting = W.WET_SURFACE_ENERGY
+    lat = _lattice([s, se])
+    assert len(lat.contact_line(0)) == 0
+    got = lat.contact_line(1)
+    n_bnd = int((_oracle(se).classes() == 1).sum())
+    assert len(got) == n_bnd == 2 * 100
+    assert set(np.unique(got[:, 1]).tolist()) == {1, 20}
