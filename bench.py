@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "fingering_large", "fingering", "droplet"])
+                    choices=["sweep", "fingering_large", "fingering", "droplet", "x8", "x9"])
     ap.add_argument("--storage", default=None, choices=["f64", "f32", "f16", "c16"])
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,6 +79,12 @@ def build_workload(name):
         return [W.cfg_fingering_large()], "f64", "fingering channel 16384 x 512, M = 50, theta = 30 deg"
     if name == "fingering":
         return [W.cfg_fingering()], "f64", "fingering channel 2000 x 100, M = 10, theta = 60 deg"
+    if name == "x8":
+        return W.cfg_x8(), "f64", ("wettability sweep of Sec. III D 2: 15 channels 630 x 60, theta 20..160,"
+                                   " M = 1, u0 = 0.1, one launch per step")
+    if name == "x9":
+        return W.cfg_x9(), "f64", ("viscosity-ratio / capillary-number sweep of Sec. III D 4: 44 channels"
+                                   " 630 x 60, M 1..1000, Ca 0.36..0.72, one launch per step")
     return [W.cfg_droplet_flat()], "f64", "static droplet on a flat wall, 200 x 100, theta = 60 deg"
 
 

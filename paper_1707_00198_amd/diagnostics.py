@@ -11,6 +11,8 @@ lbm_diag_*): no field is read back to the host.
   E = sqrt((m_R^out / m_R^all)^2 + (m_B^in / m_B^all)^2).
 * ``channel_interface``: contact line, tip and finger length of a displacement channel from the
   rho^N = 0 crossings on the rows next to the walls and on the centre line.
+* ``track_channels`` / ``rate``: S(t), L(t) of a batch of channels sampled during a run, and
+  their steady slopes (the speeds of Eqs. 50-51 and Fig. 9).
 """
 from __future__ import annotations
 
@@ -64,3 +66,32 @@ def channel_interface(lat, dom: int, solid: np.ndarray) -> dict:
     cl = None if math.isnan(x[0]) or math.isnan(x[1]) else 0.5 * (x[0] + x[1])
     tip = nan(np.mean(x[2:])) if not np.isnan(x[2:]).any() else None
     return dict(contact_line=cl, tip=tip, length=None if cl is None or tip is None else tip - cl)
+
+
+def track_channels(lat, doms, steps: int, every: int):
+    """Advance ``lat`` by ``steps`` in windows of ``every`` and record, for each domain in
+    ``doms``, the contact line and finger length of ``channel_interface`` after every window.
+    Returns (times (k,), contact line (len(doms), k), length (len(doms), k)); NaN where a row
+    has no crossing."""
+    times, cl, ln = [], [], []
+    solids = [lat.setups[d].solid for d in doms]
+    for _ in range(steps // every):
+        lat.step(every)
+        times.append(lat.steps)
+        row_cl, row_ln = [], []
+        for d, solid in zip(doms, solids):
+            m = channel_interface(lat, d, solid)
+            row_cl.append(np.nan if m["contact_line"] is None else m["contact_line"])
+            row_ln.append(np.nan if m["length"] is None else m["length"])
+        cl.append(row_cl)
+        ln.append(row_ln)
+    return np.array(times, dtype=np.float64), np.array(cl).T, np.array(ln).T
+
+
+def rate(times, values, t_min: float) -> float:
+    """Least-squares slope of ``values`` over the samples with time >= t_min (the steady
+    speeds dS/dt and dL/dt of Sec. III D)."""
+    sel = (times >= t_min) & np.isfinite(values)
+    if sel.sum() < 2:
+        return math.nan
+    return float(np.polyfit(times[sel], values[sel], 1)[0])

@@ -184,6 +184,18 @@ def fingering_channel(nx=2000, h=100, x_interface=200.0, M=10.0, theta_deg=60.0,
                  meta=dict(U=U, u0=1.5 * U, ca=ca, M=M, x_interface=x_interface))
 
 
+def paper_channel(theta_deg=90.0, M=1.0, u0=0.1, nu_r=0.3, sigma=0.06, nx=630, h=60,
+                  x_interface=30.0, name=None):
+    """The displacement channel of Sec. III D (Fig. 6): 630 x 60 fluid nodes between walls, red
+    for x < 30, Poiseuille inlet of maximum speed u0 (the paper's Ca = nu_R u0 / sigma),
+    convective outlet at the mean speed 2 u0 / 3."""
+    s = fingering_channel(nx=nx, h=h, x_interface=x_interface, M=M, theta_deg=theta_deg,
+                          ca=(2.0 / 3.0) * u0 * nu_r / sigma, nu_r=nu_r, sigma=sigma,
+                          name=name or f"paper_channel_t{theta_deg:g}_M{M:g}_u{u0:g}")
+    s.meta["ca_max"] = nu_r * u0 / sigma
+    return s
+
+
 def capillary(nx=400, ny=35, plate_x0=100, plate_x1=300, thick=7, blue_x0=120, blue_x1=375,
               theta_deg=30.0, M=1.0, nu_r=0.5, sigma=0.005):
     """Capillary filling box of Sec. III C: periodic, plates of thickness `thick` at
@@ -230,6 +242,20 @@ def cfg_fingering_large():
     interface at x = 1024."""
     return fingering_channel(nx=16384, h=512, x_interface=1024.0, M=50.0, theta_deg=30.0,
                              ca=0.2, nu_r=0.5, sigma=0.05, name="fingering_16384x512")
+
+
+def cfg_x8(thetas=tuple(range(20, 161, 10))):
+    """Sec. III D 2 (Fig. 8, Eqs. 50-51): M = 1, nu = 0.3, u0 = 0.1, sigma = 0.06 (Ca = 0.5),
+    contact angle 20..160 degrees, one channel per angle."""
+    return [paper_channel(theta_deg=float(t), M=1.0, u0=0.1, nu_r=0.3, sigma=0.06,
+                          name=f"x8_t{t}") for t in thetas]
+
+
+def cfg_x9(cas=(0.72, 0.60, 0.48, 0.36), Ms=(1, 2, 3, 5, 10, 20, 50, 100, 200, 500, 1000)):
+    """Sec. III D 4 (Figs. 9-10): theta = 90 deg, u0 = 0.01, nu_R = 0.5, nu_B = nu_R / M,
+    sigma = nu_R u0 / Ca, one channel per (Ca, M)."""
+    return [paper_channel(theta_deg=90.0, M=float(M), u0=0.01, nu_r=0.5, sigma=0.5 * 0.01 / ca,
+                          name=f"x9_ca{ca:g}_M{M}") for ca in cas for M in Ms]
 
 
 def cfg_sweep(n_channels=320, seed=SEED):

@@ -301,3 +301,32 @@ def test_eq36_ties_at_exact_mirror_symmetry():
     assert mirror_gap(W.droplet_box(theta_deg=150.0, M=10.0, nx=70, ny=50, radius=16.0)) > 1e-6
     assert mirror_gap(W.droplet_box(theta_deg=150.0, M=10.0, nx=70, ny=50, radius=16.0,
                                     xc_offset=0.37)) < 1e-12
+
+
+@pytest.mark.parametrize("theta", [30.0, 150.0])
+def test_x8_displacement_speeds_eqs_50_51(theta):
+    """Sec. III D 2 channel (630 x 60, M = 1, u0 = 0.1, sigma = 0.06): the steady contact-line
+    speed and finger growth rate agree with the printed fits Eqs. 51 and 50 (S and L exchanged:
+    printed as is, Eq. 50 would have the contact line outrun the mean injection speed for
+    theta > 108 degrees) within 12 %, and the contact line stays behind the mean speed."""
+    from paper_1707_00198_amd.diagnostics import rate
+    s = W.paper_channel(theta_deg=theta)
+    o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **s.oracle_kwargs())
+    t, S, L = [], [], []
+    for _ in range(18):
+        o.step(250)
+        rr, rb = o.field("rhoR"), o.field("rhoB")
+        tot = rr + rb
+        rn = np.where(s.solid == 0, (rr - rb) / np.where(tot > 0, tot, 1.0), 0.0)
+        m = physics.finger_metrics(rn, s.solid)
+        t.append(o.steps)
+        S.append(m["contact_line"])
+        L.append(m["length"])
+    t, S, L = np.array(t, float), np.array(S, float), np.array(L, float)
+    ds, dl = rate(t, S, 2000), rate(t, L, 2000)
+    fit_s = 3.095e-2 - 1.212e-4 * theta
+    fit_l = 5.278e-2 + 1.280e-4 * theta
+    print(f"theta {theta}: dS/dt {ds:.5f} (fit {fit_s:.5f}), dL/dt {dl:.5f} (fit {fit_l:.5f})")
+    assert abs(ds / fit_s - 1) < 0.12
+    assert abs(dl / fit_l - 1) < 0.12
+    assert ds < s.meta["U"]
