@@ -60,7 +60,7 @@ struct Layout {
     size_t buf[2] = {0, 0}, f_bytes = 0, c_off = 0, vx_off = 0, vy_off = 0, hist[2] = {0, 0};
     size_t state_bytes = 0;
     // scratch
-    size_t mask = 0, nsx = 0, nsy = 0, inlet = 0, doms = 0, items = 0, partials = 0,
+    size_t mask = 0, ns = 0, inlet = 0, doms = 0, items = 0, partials = 0,
            mass_out = 0, flag = 0, scratch_bytes = 0;
 };
 
@@ -98,10 +98,8 @@ Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
     o = 0;
     L.mask = o;
     o += align_up(L.plane * 2, 256);
-    L.nsx = o;
-    o += align_up(L.plane * cb, 256);
-    L.nsy = o;
-    o += align_up(L.plane * cb, 256);
+    L.ns = o;  // wall normal (x, y) per node, interleaved
+    o += align_up(2 * L.plane * cb, 256);
     L.inlet = o;
     o += align_up(rows * cb, 256);
     L.doms = o;
@@ -290,15 +288,14 @@ void fill_args(const lbm_ctx *c, int parity, StepArgs<T, AT> &A) {
     A.hist_in = reinterpret_cast<const AT *>(c->state + L.hist[parity]);
     A.hist_out = reinterpret_cast<AT *>(c->state + L.hist[1 - parity]);
     A.mask = reinterpret_cast<const uint16_t *>(c->scratch + L.mask);
-    A.nsx = reinterpret_cast<const AT *>(c->scratch + L.nsx);
-    A.nsy = reinterpret_cast<const AT *>(c->scratch + L.nsy);
+    A.ns = reinterpret_cast<const AT *>(c->scratch + L.ns);
     A.inlet = reinterpret_cast<const AT *>(c->scratch + L.inlet);
     A.plane = L.plane;
     A.flag = reinterpret_cast<int *>(c->scratch + L.flag);
     A.f_plane_bytes = (uint32_t)(L.plane * sizeof(T));
     A.f_set_bytes = (uint32_t)(9 * L.plane * sizeof(T));
     A.c_plane_bytes = (uint32_t)(L.vx_off - L.c_off);
-    A.ns_stride_bytes = (uint32_t)(L.nsy - L.nsx);
+    A.ns_bytes = (uint32_t)(2 * L.plane * sizeof(AT));
 }
 
 // Arguments for the current parity, as raw bytes of the storage's StepArgs instantiation.
@@ -437,7 +434,7 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
     const Layout &L = c->L;
     const size_t P = L.plane;
     std::vector<uint16_t> mask(P, (uint16_t)SELF_SOLID);
-    std::vector<AT> nsx(P, AT(0)), nsy(P, AT(0)), inlet(std::max<size_t>(L.rows, 1), AT(0));
+    std::vector<AT> ns(2 * P, AT(0)), inlet(std::max<size_t>(L.rows, 1), AT(0));
     std::vector<T> f(9 * P, encode<T>(0.0, 1.0f));
     std::vector<AT> col(3 * P, AT(0));  // c, vx, vy
     std::vector<AT> hist(3 * std::max<size_t>(L.rows, 1), AT(0));
@@ -481,8 +478,8 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
                 const bool s = (m & SELF_SOLID) != 0;
                 n_fluid_bnd += (m & FLUID_BND) ? 1 : 0;
                 mask[g] = (uint16_t)m;
-                nsx[g] = (AT)vx;
-                nsy[g] = (AT)vy;
+                ns[2 * g] = (AT)vx;
+                ns[2 * g + 1] = (AT)vy;
                 if (s) continue;
                 const double rr = q.rho_r0[k], rb = q.rho_b0[k], rho = rr + rb;
                 for (int a = 0; a < 9; a++)
@@ -509,8 +506,7 @@ int create_t(lbm_ctx *c, const lbm_domain_desc *d) {
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipMemsetAsync(c->scratch, 0, L.scratch_bytes, s));
     HIP_OK(hipMemcpyAsync(c->scratch + L.mask, mask.data(), P * 2, hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(c->scratch + L.nsx, nsx.data(), P * sizeof(AT), hipMemcpyHostToDevice, s));
-    HIP_OK(hipMemcpyAsync(c->scratch + L.nsy, nsy.data(), P * sizeof(AT), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync(c->scratch + L.ns, ns.data(), 2 * P * sizeof(AT), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(c->scratch + L.inlet, inlet.data(), L.rows * sizeof(AT),
                           hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync(c->scratch + L.doms, c->doms.data(), c->n * sizeof(DomDev),
@@ -541,10 +537,10 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     int rc = validate(domains, n, storage);
     if (rc) return rc;
     Layout L = make_layout(domains, n, storage);
-    // The step kernel addresses the 9 population planes, the 3 colour-state planes and the 2
-    // wall-normal planes each as one buffer of fewer than 2^31 bytes.
+    // The step kernel addresses the 9 population planes, the 3 colour-state planes and the
+    // interleaved wall normals each as one buffer of fewer than 2^31 bytes.
     if (L.f_bytes >= (size_t(1) << 31) || 3 * (L.vx_off - L.c_off) >= (size_t(1) << 31) ||
-        2 * (L.nsy - L.nsx) >= (size_t(1) << 31))
+        2 * L.plane * (storage == 0 ? 8 : 4) >= (size_t(1) << 31))
         return fail(LBM_EINVAL,
                     "%zu nodes exceed one context's limit (2^31 bytes for the 9 population planes "
                     "and for the 3 colour-state planes); split the domains over several contexts",

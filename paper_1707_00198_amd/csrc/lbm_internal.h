@@ -73,18 +73,18 @@ struct StepArgs {
     const AT *hist_in;
     AT *hist_out;
     const uint16_t *mask;
-    const AT *nsx, *nsy;
+    const AT *ns;  // wall normal (x, y) per node, interleaved
     const AT *inlet;
     size_t plane;
     int *flag;
     // Byte extents for the step kernel's buffer accesses (each below 2^31, checked on the
     // host): one population plane, the 9 population planes, one colour-state plane (c, vx and
-    // vy planes follow each other at this stride), and the offset of nsy after nsx.
-    uint32_t f_plane_bytes, f_set_bytes, c_plane_bytes, ns_stride_bytes;
+    // vy planes follow each other at this stride), and the interleaved wall normals.
+    uint32_t f_plane_bytes, f_set_bytes, c_plane_bytes, ns_bytes;
     // Diagnostic launch (diag != 0): the state is read as in a step but nothing is written
     // back (no populations, colour state or outlet history); instead the velocity of Eq. 17
     // (with the half-force term) of every fluid node goes to u_out, u_x then u_y, planes
-    // c_plane_bytes apart.
+    // c_plane_bytes apart (through the colour-state stores of the step).
     AT *u_out;
     int diag;
     // Contact-line list of a diagnostic launch (cl_count == nullptr: none): every outermost

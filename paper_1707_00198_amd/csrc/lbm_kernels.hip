@@ -475,6 +475,20 @@ struct Buf<float> {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
     }
 };
+// Two consecutive values (the interleaved wall normal of a node) in one load.
+template <class V>
+struct Pair {
+    V x, y;
+};
+// (The whole loaded vector is bit-cast: a bit-cast of one element of it, as in
+// __builtin_bit_cast(float, v[1]), was compiled as a read of element 0.)
+__device__ __forceinline__ Pair<float> load_pair(Rsrc r, uint32_t vo, float) {
+    return __builtin_bit_cast(Pair<float>, __builtin_amdgcn_raw_buffer_load_b64(r, vo, 0, 0));
+}
+__device__ __forceinline__ Pair<double> load_pair(Rsrc r, uint32_t vo, double) {
+    return __builtin_bit_cast(Pair<double>, __builtin_amdgcn_raw_buffer_load_b128(r, vo, 0, 0));
+}
+
 template <>
 struct Buf<__half> {
     __device__ static __half load(Rsrc r, uint32_t vo, uint32_t so) {
@@ -555,10 +569,12 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
 
     // a diagnostic launch writes no state (zero extents drop every store) but the velocity
     const Rsrc f_in = make_rsrc(A.fin, A.f_set_bytes), f_out = make_rsrc(A.fout, A.diag ? 0u : A.f_set_bytes);
-    const Rsrc c_in = make_rsrc(A.cin, 3 * A.c_plane_bytes), c_out = make_rsrc(A.cout, A.diag ? 0u : 3 * A.c_plane_bytes);
-    const Rsrc u_out = make_rsrc(A.u_out, A.diag ? 2 * A.c_plane_bytes : 0u);
+    // a diagnostic launch writes (u_x, u_y) through the colour-state stores: their resource is
+    // then the velocity buffer, whose two-plane extent drops the third store
+    const Rsrc c_in = make_rsrc(A.cin, 3 * A.c_plane_bytes);
+    const Rsrc c_out = A.diag ? make_rsrc(A.u_out, 2 * A.c_plane_bytes) : make_rsrc(A.cout, 3 * A.c_plane_bytes);
     const Rsrc r_mask = make_rsrc(A.mask, (uint32_t)A.plane * 2u);
-    const Rsrc r_ns = make_rsrc(A.nsx, 2 * A.ns_stride_bytes);
+    const Rsrc r_ns = make_rsrc(A.ns, A.ns_bytes);
     const uint32_t FP = A.f_plane_bytes, CP = A.c_plane_bytes;
 
     auto row_ok_a = [&](int y) { return y >= y0 - HALO + 1 && y < y1 + HALO - 1; };
@@ -570,14 +586,14 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     // Prefetched inputs of one stage A row ya: pulled populations (pulls from solid nodes
     // redirected to the node's own opposite population), its class word and the wall normal on
     // outermost fluid nodes; qm carries the class word of the row, loaded by the previous
-    // prefetch.  The set is issued one iteration before its stage A.  (A second set issued two
-    // iterations ahead was measured slower: with the stores in between, the vector memory
-    // operations in flight exceed what the wait counter expresses, and the compiler then waits
-    // for the newest stores.)  The colour state that stage D puts into LDS for a stage A row is
-    // loaded at the top of the iteration before: vector memory instructions complete in order,
-    // stores included, so it then has a full iteration (and never waits for the stores of the
-    // stage E in between).  Two colour register sets alternate between iterations (the loop is
-    // unrolled twice).
+    // prefetch.  The set is issued one iteration before its stage A; an iteration issues 26
+    // vector memory operations (3 colour loads, 12 stores, 11 prefetch loads).  (A second set
+    // issued two iterations ahead measured no faster, and the compiler's waits for it were not
+    // exact.)  The colour state that stage D puts into LDS for a stage A row is loaded at the
+    // top of the iteration before: vector memory instructions complete in order, stores
+    // included, so it then has a full iteration (and never waits for the stores of the stage E
+    // in between).  Two colour register sets alternate between iterations (the loop is unrolled
+    // twice).
     struct Pre {
         T f[9];
         uint32_t m;
@@ -602,33 +618,64 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     auto load_mask = [&](int y) {
         qm = Buf<uint16_t>::load(r_mask, row_ok_a(y) ? node_of(y) * 2u : NOWHERE, 0);
     };
+    // Column part of the pull offsets (x - 1, x, x + 1; NOWHERE outside the gather lanes), for
+    // the prefetch's fast path.
+    uint32_t colv[3];
+    {
+        const Nbr nb0 = make_nbr(D, xe, 0);
+#pragma unroll
+        for (int k = 0; k < 3; k++) colv[k] = gather_lane ? (uint32_t)nb0.col[k] * SB : NOWHERE;
+    }
     auto prefetch = [&](int ya, Pre &p) {
         const bool ok = row_ok_a(ya);
         const uint32_t m = ok ? qm : SELF_SOLID;
-        const bool act = gather_lane && !(m & SELF_SOLID);
         Nbr nb = make_nbr(D, xe, wrap(ya, D.ny));
-        const uint32_t self = (uint32_t)nb.row[1] + (uint32_t)xe;
-        const uint32_t vw = act && (m & FLUID_BND) ? self * CB : NOWHERE;
-        p.wx = Buf<AT>::load(r_ns, vw, 0);
-        p.wy = Buf<AT>::load(r_ns, vw, A.ns_stride_bytes);
-        // snapshot state: every population is the node's own, none bounces
-        const uint32_t solid_nbrs = A.own ? 0u : m;
-        if (A.own) {
-            nb.row[0] = nb.row[2] = nb.row[1];
-            nb.col[0] = nb.col[2] = xe;
-            nb.lo = nb.hi = false;
-        }
+        // Fast path: no node of the tile row is solid or has a solid neighbour (nothing bounces,
+        // every gather lane pulls), the state is not a snapshot and the tile has no open edge.
+        // Then a pull's offset is the lane's column plus a wave-uniform row and plane offset,
+        // with no vector arithmetic per population.  The branch only chooses offsets: one set
+        // of loads follows, so the waits after it stay exact.  Only the FP32-arithmetic kernels
+        // take it: they are bound by vector instruction issue; the FP64 kernel is not, and the
+        // extra registers would cost it an occupancy step.
+        const bool fast = sizeof(AT) == 4 && ok && !A.own && !edge_item &&
+                          __builtin_amdgcn_ballot_w64((m & (SELF_SOLID | 0xFFu)) != 0u) == 0;
+        uint32_t vo[9], so[9], vw;
+        if (fast) {
+            vw = NOWHERE;
 #pragma unroll
-        for (int a = 0; a < 9; a++) {
-            // Direction a and its opposite share the plane offset of the lower of the two;
-            // the per-lane offset adds two planes for the higher one (opposites are 2 apart).
-            const int lo = a < OPP[a] ? a : OPP[a];
-            const uint32_t up = a == lo ? 0u : 2u * FP;
-            uint32_t vo = (uint32_t)pull_src(nb, a) * SB + up;
-            if (a > 0 && !pull_outside(nb, a) && (solid_nbrs & (1u << (OPP[a] - 1))))
-                vo = self * SB + (2u * FP - up);
-            p.f[a] = Buf<T>::load(f_in, act ? vo : NOWHERE, (uint32_t)lo * FP);
+            for (int a = 0; a < 9; a++) {
+                vo[a] = colv[1 - EX[a]];
+                so[a] = (uint32_t)a * FP + (uint32_t)nb.row[1 - EY[a]] * SB;
+            }
+        } else {
+            const bool act = gather_lane && !(m & SELF_SOLID);
+            const uint32_t self = (uint32_t)nb.row[1] + (uint32_t)xe;
+            vw = act && (m & FLUID_BND) ? self * (2 * CB) : NOWHERE;
+            // snapshot state: every population is the node's own, none bounces
+            const uint32_t solid_nbrs = A.own ? 0u : m;
+            if (A.own) {
+                nb.row[0] = nb.row[2] = nb.row[1];
+                nb.col[0] = nb.col[2] = xe;
+                nb.lo = nb.hi = false;
+            }
+#pragma unroll
+            for (int a = 0; a < 9; a++) {
+                // Direction a and its opposite share the plane offset of the lower of the two;
+                // the per-lane offset adds two planes for the higher one (opposites are 2 apart).
+                const int lo = a < OPP[a] ? a : OPP[a];
+                const uint32_t up = a == lo ? 0u : 2u * FP;
+                uint32_t v = (uint32_t)pull_src(nb, a) * SB + up;
+                if (a > 0 && !pull_outside(nb, a) && (solid_nbrs & (1u << (OPP[a] - 1))))
+                    v = self * SB + (2u * FP - up);
+                vo[a] = act ? v : NOWHERE;
+                so[a] = (uint32_t)lo * FP;
+            }
         }
+        const Pair<AT> wn = load_pair(r_ns, vw, AT());
+        p.wx = wn.x;
+        p.wy = wn.y;
+#pragma unroll
+        for (int a = 0; a < 9; a++) p.f[a] = Buf<T>::load(f_in, vo[a], so[a]);
         p.m = m;
         load_mask(ya + R);
     };
@@ -899,11 +946,11 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
                 vc = nd * CB;
                 if (!isfinite(rho + ux + uy)) atomicOr(A.flag, 1);  // any NaN or overflow
             }
-            store_row(vf, vc, o, c, bx, by);
             if (A.diag) {
-                Buf<AT>::store(u_out, vc, 0, ux);
-                Buf<AT>::store(u_out, vc, CP, uy);
+                c = ux;
+                bx = uy;
             }
+            store_row(vf, vc, o, c, bx, by);
         }
 #pragma unroll
         for (int a = 0; a < 9; a++) d[a] = dn[a];
@@ -919,8 +966,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     };
     // Both exits test the row bound themselves: an exit merged into a shared loop test would
     // put a path from the first half back to the loop head, where the compiler would then take
-    // the first half's prefetch as possibly still in flight.
-    if (r_first >= y1) return;
+    // the first half's prefetch as possibly still in flight.  (r_first < y0 < y1.)
     for (int r = r_first;; r += 2 * R) {
         iteration(r, std::integral_constant<int, 0>());
         if (r + R >= y1) break;

@@ -178,3 +178,33 @@ def test_checkpoint_roundtrip_is_bitwise():
     assert lat.steps == 15
     pb = lat.step(25).pops(0)
     assert np.array_equal(pa, pb)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "c16"])
+def test_reduced_storage_one_step_from_gpu_state(storage):
+    """The FP32-arithmetic paths, one step at a time: after 30 steps the GPU state is read back,
+    the oracle advances it by one step, and the GPU's own next step must agree within the
+    storage's rounding of each population's deviation from w rho0 (2^-22 for FP32, 2^-11 for
+    binary16, 2^-12 for the 11-bit-fraction format) plus 2e-6 for FP32 arithmetic, on channels
+    (walls, inlet, outlet, bounce-back, wetting), a flat-wall droplet and a cylinder."""
+    weights = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    rel = {"f32": 2.0 ** -22, "f16": 2.0 ** -11, "c16": 2.0 ** -12}[storage]
+    setups = [W.fingering_channel(nx=300, h=75, x_interface=150.0, M=10.0, theta_deg=60.0,
+                                  ca=0.1, nu_r=0.5, sigma=0.05, name="c75"),
+              W.fingering_channel(nx=260, h=50, x_interface=100.0, M=2.0, theta_deg=120.0,
+                                  ca=0.2, nu_r=0.5, sigma=0.05, name="c50"),
+              W.droplet_flat(nx=180, h=60, radius=20.0, theta_deg=60.0, xc=77.3, name="drop"),
+              W.cylinder_droplet(n=96, rc=20.0, rd=18.0, theta_deg=120.0, ccx=48.0, ccy=30.0,
+                                 name="cyl", dcx_offset=0.37)]
+    lat = lattice(setups, storage).step(30)
+    before = [lat.pops(d) for d in range(len(setups))]
+    lat.step(1)
+    for d, s in enumerate(setups):
+        o = oracle_for(s)
+        o.set_pops(before[d])
+        ref = o.step(1).pops()
+        got = lat.pops(d)
+        dev = np.abs(ref.sum(axis=0) - weights[:, None, None] * s.params["rho0"] * (s.solid == 0))
+        worst = (np.abs(got - ref) / (dev * rel + 2e-6)[None]).max()
+        print(f"{storage} {s.name}: max error / tolerance = {worst:.3f}", flush=True)
+        assert np.isfinite(got).all() and worst <= 1.0
