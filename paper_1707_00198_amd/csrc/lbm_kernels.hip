@@ -11,9 +11,10 @@
 //                destination from the source node's (c, v) - an exact rewrite of Eqs. 14-16
 //                that stores 12 values per node instead of 18.
 //
-// The step kernel marches a 64-column window (56 output columns plus a 4-column halo on each
-// side) up a chunk of rows.  Every iteration advances four rows through five stages kept in
-// LDS ring buffers, each lagging the previous one by a row:
+// The step kernel marches a 64-column window (54 output columns plus a 5-column halo on each
+// side: the dependency radius next to walls is 4, plus one column for the colour-state stencil)
+// up a chunk of rows.  Every iteration advances R rows (4 by default) through five stages kept
+// in LDS ring buffers, each lagging the previous one by a row:
 //   A  pull the 9 populations (bounce-back, inlet and outlet completion), rho_R, rho_B, rho^N
 //   B  virtual rho^N on outermost solid nodes (Eq. 29)
 //   C  colour gradient (Eq. 28), wetting correction on outermost fluid nodes (Eqs. 30-36),
@@ -24,6 +25,9 @@
 // Stage E of a row runs on the same thread that did stage A of that row one iteration
 // earlier, so the populations stay in registers: each population is read once from HBM and
 // written once per step (halo columns are re-read by the neighbouring window, from cache).
+// Per-domain wetting variants of Sec. III A (scheme (b), Eq. 48; the surface-energy rule)
+// change stages B-E.  A diagnostic launch runs the same kernel without writing the state and
+// outputs the velocity of Eq. 17 and, optionally, the contact-line nodes instead.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -960,7 +964,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
         // Stage A of the next iteration, without a barrier: it writes s_m / s_rn rows
         // r + 2R .. r + 3R - 1, which alias rows r .. r + R - 1; of those, stage E reads only
         // s_m of its own row, written by its own wavefront.  The colour rows it reads were
-        // written in stage D, before the last barrier.
+        // put into LDS after stage D, before the last barrier.
         stage_a(r + 2 * R + w, pre);
         prefetch(r + 3 * R + w, pre);
     };
