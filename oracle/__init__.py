@@ -132,11 +132,13 @@ class Oracle:
                                None if nsa is None else _dp(nsa), _dp(iu), _dp(rr), _dp(rb))
         if not self._h:
             raise ValueError("oracle rejected the parameters")
+        # held by the object: module globals may already be gone when it is collected at exit
+        self._destroy = L.orc_destroy
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def step(self, n=1):

@@ -159,12 +159,14 @@ class Lattice:
                                 st.value, self.scratch_buf.data_ptr(), sc.value,
                                 C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
+        # held by the object: module globals may already be gone when it is collected at exit
+        self._destroy = L.lbm_destroy
         self.state_bytes, self.scratch_bytes = st.value, sc.value
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            load_library().lbm_destroy(h)
+            self._destroy(h)
             self._h = None
 
     # ----------------------------------------------------------------- stepping
