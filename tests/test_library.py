@@ -104,6 +104,32 @@ def test_wetting_flags_validated():
     assert rc == -1 and "wetting" in err
 
 
+def test_empty_batch_is_rejected():
+    L = lbm.load_library()
+    st, sc = C.c_size_t(), C.c_size_t()
+    assert L.lbm_query_bytes(None, 0, 0, C.byref(st), C.byref(sc)) == -1
+    assert "at least one domain" in L.lbm_last_error().decode()
+
+
+def test_context_beyond_the_buffer_limit_is_rejected_before_device_work():
+    """The step kernel addresses the 9 population planes as one buffer below 2^31 bytes: an
+    FP64 batch of more than 2^31 / 72 nodes is refused by lbm_create with a clear message, before
+    any device buffer is touched (NULL buffers here), while FP32 storage of the same batch fits."""
+    ny, nx = 5002, 6000  # 30.0 M nodes: 9 x 8 B x 30 M > 2^31, 9 x 4 B x 30 M < 2^31
+    solid = np.zeros((ny, nx), np.uint8)
+    solid[0, :] = solid[-1, :] = 1
+    rr = np.where(solid == 0, 1.0, 0.0)
+    rb = np.zeros_like(rr)
+    s = W.Setup("huge", solid, rr, rb, W._phys())
+    L = lbm.load_library()
+    d, keep = _desc(s)
+    h = C.c_void_p()
+    rc = L.lbm_create(C.byref(d), 1, 0, None, 0, None, 0, None, C.byref(h))
+    assert rc == -1 and "context's limit" in L.lbm_last_error().decode()
+    rc = L.lbm_create(C.byref(d), 1, 1, None, 0, None, 0, None, C.byref(h))
+    assert rc == -1 and "NULL" in L.lbm_last_error().decode()
+
+
 def test_lattice_refuses_without_gpu():
     import torch
     if torch.cuda.is_available():
