@@ -117,8 +117,29 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
  * (Eqs. 32-33 or the caller's analytic normal, unit length, into the solid), 0 elsewhere. */
 int lbm_classify(const lbm_domain_desc *domain, uint8_t *classes_out, double *ns_out);
 
-/* Enqueue n_steps time steps of every domain on the context's stream (asynchronous). */
+/* Enqueue n_steps time steps of every domain on the context's stream (asynchronous).  With
+ * step graphs on (lbm_set_graph), runs of steps go out as replays of an instantiated HIP graph
+ * of that many step launches; results are the same bit for bit either way. */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);
+
+/* Step graphs: `launches` step launches (0 = off, the default, else even, 2..1024) are
+ * captured once per starting buffer parity on a private stream of the library and replayed on
+ * the context's stream, one graph launch per `launches` steps.  The initial state of a context
+ * (node-local, not yet streamed; also after lbm_load_state of such a state) first takes one
+ * direct step, and a remainder shorter than a graph is launched step by step.  The graphs are rebuilt after lbm_set_tile and
+ * lbm_autotune.  Synchronises the stream.  LBM_EINVAL for an odd or out-of-range count. */
+int lbm_set_graph(lbm_ctx *ctx, int launches);
+
+/* Autotuner of the step's tile shape on this context's own batch: times every provided shape,
+ * chunk_rows in {8, 12, 16, 24, 32, 48, 64} (shapes that cut no domain differently are timed
+ * once) x (waves, cols) in {(4, 1), (8, 1), (4, 2)}, with `steps` (1..100000) timed steps after
+ * one untimed step each, re-times the three fastest and keeps the fastest (as lbm_set_tile).
+ * The trials run real steps, so the state is first saved to `save_dev` (caller-owned device
+ * buffer of lbm_state_size bytes) and restored afterwards: the state, the step count and the
+ * non-finite flag are as before the call, and results never depend on the tile shape.  If
+ * `out_host` is not NULL it receives (chunk_rows, waves, cols, milliseconds per step) of the
+ * choice.  Synchronises the stream.  On LBM_EDEVICE the state is undefined. */
+int lbm_autotune(lbm_ctx *ctx, int steps, void *save_dev, double *out_host);
 
 /* Field selection bits for lbm_read_fields. */
 #define LBM_FIELD_RHO_R 1u   /* red density, Eq. 16 (one plane) */

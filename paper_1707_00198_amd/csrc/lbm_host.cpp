@@ -265,6 +265,11 @@ struct lbm_ctx {
     int *rows_host = nullptr;
     bool snap_valid = false;
     int max_fluid_bnd = 0;  // largest number of outermost fluid nodes in one domain
+    // step graphs: `graph_steps` step launches captured once on a private stream, one graph per
+    // parity a replay starts from (graph_steps is even, so a replay ends on the same parity)
+    int graph_steps = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -431,6 +436,53 @@ int upload_items(lbm_ctx *c) {
     HIP_OK(hipMemcpyAsync(c->scratch + c->L.items, c->items.data(),
                           c->items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+// One step launched directly on stream s, with the context's current arguments.
+hipError_t step_once(lbm_ctx *c, hipStream_t s) {
+    AnyArgs a = make_args(c, c->parity);
+    const hipError_t e = launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->cols,
+                                     c->variants, s);
+    if (e != hipSuccess) return e;
+    c->parity ^= 1;
+    c->own = 0;
+    c->steps++;
+    return hipSuccess;
+}
+
+void drop_graphs(lbm_ctx *c) {
+    for (auto &g : c->gexec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+// Capture graph_steps step launches starting from `parity` (the state then being no snapshot)
+// on the private stream and instantiate them.  The context's parity, flags and step count are
+// left as they were: lbm_step advances them per replay.
+int build_graph(lbm_ctx *c, int parity) {
+    if (!c->cap) HIP_OK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    const int p0 = c->parity, own0 = c->own;
+    const int64_t s0 = c->steps;
+    c->parity = parity;
+    c->own = 0;
+    HIP_OK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < c->graph_steps && e == hipSuccess; k++) e = step_once(c, c->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+    c->parity = p0;
+    c->own = own0;
+    c->steps = s0;
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiateWithFlags(&c->gexec[parity], g, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec[parity] = nullptr;
+        return fail(LBM_EDEVICE, "step graph: %s", hipGetErrorString(e));
+    }
     return LBM_OK;
 }
 
@@ -609,12 +661,122 @@ int lbm_classify(const lbm_domain_desc *domain, uint8_t *classes_out, double *ns
 int lbm_step(lbm_ctx *c, int64_t n_steps) {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (n_steps < 0) return fail(LBM_EINVAL, "negative step count");
-    for (int64_t k = 0; k < n_steps; k++) {
-        AnyArgs a = make_args(c, c->parity);
-        HIP_OK(launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
-        c->parity ^= 1;
-        c->own = 0;
-        c->steps++;
+    while (n_steps > 0) {
+        // A replay needs the steady state of the arguments: a snapshot state (own) takes one
+        // direct step first, and a remainder shorter than a graph is launched step by step.
+        const int G = c->graph_steps;
+        if (G > 0 && !c->own && n_steps >= G) {
+            if (!c->gexec[c->parity]) {
+                const int rc = build_graph(c, c->parity);
+                if (rc) return rc;
+            }
+            HIP_OK(hipGraphLaunch(c->gexec[c->parity], c->stream));
+            c->steps += G;
+            n_steps -= G;
+            continue;
+        }
+        HIP_OK(step_once(c, c->stream));
+        n_steps--;
+    }
+    return LBM_OK;
+}
+
+int lbm_set_graph(lbm_ctx *c, int launches) {
+    if (!c) return fail(LBM_EINVAL, "null context");
+    if (launches != 0 && (launches < 2 || launches > 1024 || launches % 2))
+        return fail(LBM_EINVAL, "launches per graph must be 0 or an even number in [2, 1024]");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->graph_steps = launches;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
+    if (!c || !save_dev) return fail(LBM_EINVAL, "null argument");
+    if (steps < 1 || steps > 100000) return fail(LBM_EINVAL, "steps per trial must be in [1, 100000]");
+    int rc = lbm_save_state(c, save_dev);
+    if (rc) return rc;
+    HIP_OK(hipMemcpyAsync(c->flag_host, c->scratch + c->L.flag, sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const int flag0 = *c->flag_host;
+    struct Trial {
+        int chunk, waves, cols;
+        double ms;
+    };
+    std::vector<Trial> trials;
+    const int shapes[3][2] = {{4, 1}, {8, 1}, {4, 2}};  // (waves, cols)
+    for (const auto &sh : shapes) {
+        std::vector<WorkItem> prev;
+        for (int ch : {8, 12, 16, 24, 32, 48, 64}) {
+            std::vector<WorkItem> it = build_items(c->desc, ch, sh[1]);
+            // a taller chunk that cuts no domain differently is the same schedule
+            if (it.size() == prev.size() &&
+                std::equal(it.begin(), it.end(), prev.begin(), [](const WorkItem &a, const WorkItem &b) {
+                    return a.dom == b.dom && a.x0 == b.x0 && a.y0 == b.y0 && a.y1 == b.y1;
+                }))
+                continue;
+            trials.push_back({ch, sh[0], sh[1], 0.0});
+            prev.swap(it);
+        }
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LBM_EDEVICE, "hipEventCreate failed");
+    }
+    // one untimed step, then `steps` timed steps on the stream, per shape
+    auto time_shape = [&](const Trial &t, double &ms) -> hipError_t {
+        c->chunk_rows = t.chunk;
+        c->waves = t.waves;
+        c->cols = t.cols;
+        c->items = build_items(c->desc, t.chunk, t.cols);
+        if (upload_items(c)) return hipErrorInvalidValue;
+        hipError_t e = step_once(c, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int k = 0; k < steps && e == hipSuccess; k++) e = step_once(c, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        ms = f / steps;
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    for (auto &t : trials)
+        if (e == hipSuccess) e = time_shape(t, t.ms);
+    // the three fastest again, ranked by the sum of both timings
+    std::sort(trials.begin(), trials.end(), [](const Trial &a, const Trial &b) { return a.ms < b.ms; });
+    const size_t top = std::min<size_t>(3, trials.size());
+    for (size_t i = 0; i < top && e == hipSuccess; i++) {
+        double ms = 0.0;
+        e = time_shape(trials[i], ms);
+        trials[i].ms += ms;
+    }
+    std::sort(trials.begin(), trials.begin() + top, [](const Trial &a, const Trial &b) { return a.ms < b.ms; });
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "autotune: %s", hipGetErrorString(e));
+    const Trial best = trials[0];
+    c->chunk_rows = best.chunk;
+    c->waves = best.waves;
+    c->cols = best.cols;
+    c->items = build_items(c->desc, best.chunk, best.cols);
+    rc = upload_items(c);
+    if (rc) return rc;
+    drop_graphs(c);
+    rc = lbm_load_state(c, save_dev);
+    if (rc) return rc;
+    *c->flag_host = flag0;
+    HIP_OK(hipMemcpyAsync(c->scratch + c->L.flag, c->flag_host, sizeof(int), hipMemcpyHostToDevice,
+                          c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    if (out_host) {
+        out_host[0] = best.chunk;
+        out_host[1] = best.waves;
+        out_host[2] = best.cols;
+        out_host[3] = best.ms / 2.0;  // mean of the two timings
     }
     return LBM_OK;
 }
@@ -676,6 +838,7 @@ int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves, int cols) {
     const int w = waves ? waves : default_waves(c->storage), k = cols ? cols : default_cols(c->storage);
     if (w == 8 && k == 2) return fail(LBM_EINVAL, "tiles of 8 x 2 wavefronts are not provided");
     HIP_OK(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
     c->waves = w;
     c->cols = k;
     c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc, c->cols);
@@ -823,6 +986,8 @@ int lbm_diag_contact_line(lbm_ctx *c, int domain, int32_t *out_host, int cap, in
 void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->mass_host) (void)hipHostFree(c->mass_host);
     if (c->flag_host) (void)hipHostFree(c->flag_host);
     if (c->diag_host) (void)hipHostFree(c->diag_host);

@@ -55,6 +55,8 @@ PROTOTYPES = {
     "lbm_mass": (C.c_int, [C.c_void_p, _dp]),
     "lbm_steps_taken": (C.c_int64, [C.c_void_p]),
     "lbm_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
+    "lbm_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
     "lbm_state_size": (C.c_size_t, [C.c_void_p]),
     "lbm_save_state": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lbm_load_state": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -180,6 +182,21 @@ class Lattice:
 
     def set_tile(self, chunk_rows: int = 0, waves: int = 0, cols: int = 0):
         _check(load_library().lbm_set_tile(self._h, int(chunk_rows), int(waves), int(cols)))
+
+    def set_graph(self, launches: int):
+        """Replay runs of `launches` steps (even; 0 = off) as one HIP graph launch each."""
+        _check(load_library().lbm_set_graph(self._h, int(launches)))
+        return self
+
+    def autotune(self, steps: int = 20) -> dict:
+        """Time every tile shape on this batch and keep the fastest; the state is saved to a
+        temporary device buffer and restored, so the simulation is unchanged."""
+        n = int(load_library().lbm_state_size(self._h))
+        buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        out = (C.c_double * 4)()
+        _check(load_library().lbm_autotune(self._h, int(steps), C.c_void_p(buf.data_ptr()), out))
+        del buf
+        return dict(chunk_rows=int(out[0]), waves=int(out[1]), cols=int(out[2]), ms_per_step=out[3])
 
     def synchronize(self):
         self.stream.synchronize()

@@ -104,6 +104,13 @@ def test_wetting_flags_validated():
     assert rc == -1 and "wetting" in err
 
 
+def test_graph_and_autotune_reject_null_arguments():
+    L = lbm.load_library()
+    assert L.lbm_set_graph(None, 8) == -1 and "null context" in L.lbm_last_error().decode()
+    out = (C.c_double * 4)()
+    assert L.lbm_autotune(None, 5, None, out) == -1 and "null" in L.lbm_last_error().decode()
+
+
 def test_empty_batch_is_rejected():
     L = lbm.load_library()
     st, sc = C.c_size_t(), C.c_size_t()
