@@ -50,6 +50,17 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_sanitize_check(out: str = None) -> str:
+    """Compile ``sanitize_check.c`` (the oracle driven over every entry point and the test
+    geometries) with gcc's address and undefined-behaviour sanitizers into an executable."""
+    out = out or os.path.join(_HERE, "sanitize_check")
+    subprocess.check_call(["gcc", "-std=gnu11", "-O1", "-g", "-fno-omit-frame-pointer",
+                           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-Wall",
+                           "-Wno-unknown-pragmas",
+                           "-I", _HERE, "-o", out, os.path.join(_HERE, "sanitize_check.c"), "-lm"])
+    return out
+
+
 _lib = None
 
 
