@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--chunk-rows", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the tile shape of the timed lattice with lbm_autotune first (its trial "
+                         "launches are step kernels too: leave it off when profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 2 GiB read + 2 GiB write elementwise kernel, the "
                          "reference for scaling HBM byte counters")
@@ -88,12 +91,17 @@ def build_workload(name):
     return [W.cfg_droplet_flat()], "f64", "static droplet on a flat wall, 200 x 100, theta = 60 deg"
 
 
-def time_lattice(setups, storage, steps, warmup, chunk_rows=0):
+def time_lattice(setups, storage, steps, warmup, chunk_rows=0, autotune=False):
     import torch
     from paper_1707_00198_amd.lbm import Lattice
     lat = Lattice(setups, storage=storage)
+    tile = "built-in rule"
     if chunk_rows:
         lat.set_tile(chunk_rows)
+        tile = {"chunk_rows": chunk_rows}
+    if autotune:
+        tile = lat.autotune(steps=10)
+        print(f"[bench] autotuned tile: {tile}", flush=True)
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -111,7 +119,7 @@ def time_lattice(setups, storage, steps, warmup, chunk_rows=0):
     del lat
     torch.cuda.empty_cache()
     return dict(fluid=fluid, event_ms=ev_ms, wall_s=wall, mlups=fluid * steps / (ev_ms * 1e-3) / 1e6,
-                ms_per_step=ev_ms / steps, mass=mass)
+                ms_per_step=ev_ms / steps, mass=mass, tile=tile)
 
 
 def measured_traffic(path, workload, storage):
@@ -172,7 +180,7 @@ def main():
         storage = args.storage
     print(f"[bench] workload {args.workload}: {len(setups)} domains, "
           f"{sum(s.fluid_nodes for s in setups)} fluid nodes, storage {storage}", flush=True)
-    head = time_lattice(setups, storage, args.steps, args.warmup, args.chunk_rows)
+    head = time_lattice(setups, storage, args.steps, args.warmup, args.chunk_rows, args.autotune)
     print(f"[bench] {args.workload} {storage}: {head['mlups']:.1f} MLUPS, "
           f"{head['ms_per_step']:.4f} ms/step", flush=True)
     del setups
@@ -212,7 +220,7 @@ def main():
         "dtype": ARITH[storage],
         "data": "synthetic",
         "config": {"workload": desc, "storage": storage, "domains": len(head["mass"]),
-                   "fluid_nodes": head["fluid"]},
+                   "fluid_nodes": head["fluid"], "tile": head["tile"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
