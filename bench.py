@@ -149,16 +149,25 @@ def cpu_baseline(seconds):
                             nu_r=0.5, sigma=0.05)
     o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **s.oracle_kwargs())
     o.step(5)
-    n, t = 0, 0.0
-    chunk = 20
-    while t < seconds:
-        t0 = time.perf_counter()
-        o.step(chunk)
-        t += time.perf_counter() - t0
-        n += chunk
-    return dict(value=s.fluid_nodes * n / t / 1e6, unit="MLUPS", cores=oracle.threads(),
-                kind="oracle",
-                sample=f"one 800 x 50 fingering channel of the sweep, {n} steps in {t:.1f} s, FP64")
+
+    def rate(budget):
+        n, t = 0, 0.0
+        while t < budget:
+            t0 = time.perf_counter()
+            o.step(20)
+            t += time.perf_counter() - t0
+            n += 20
+        return n, t
+
+    cores = oracle.threads()
+    n, t = rate(seconds)
+    # the same oracle on one thread, for a fifth of the time
+    oracle.set_threads(1)
+    n1, t1 = rate(seconds / 5.0)
+    oracle.set_threads(cores)
+    return dict(value=s.fluid_nodes * n / t / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"one 800 x 50 fingering channel of the sweep, {n} steps in {t:.1f} s, FP64",
+                value_one_thread=round(s.fluid_nodes * n1 / t1 / 1e6, 3))
 
 
 def main():
