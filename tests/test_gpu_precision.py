@@ -5,6 +5,9 @@ fraction, both with per-direction power-of-two scales, FP32 colour state and ari
 reproduce the FP64 path's physics:
   - static contact angle (the Table I flat-wall droplets) within 0.5 degrees;
   - finger length of a displacement channel (tip minus contact line) within 1 %.
+The tip velocity over the last 2000 steps of the finger runs is within 1 % of the FP64 one for
+FP32 and c16 storage (measured: 0.00 % and up to 0.26 %); binary16 is reported and bounded at
+3 % (measured: up to 2.0 %), like its finger length.
 Colour-mass drift is printed for the record and only bounded loosely: the FP64 path conserves
 it to rounding (tests/test_gpu_parity.py), the reduced paths round every stored population.
 """
@@ -57,16 +60,26 @@ def droplet_runs():
     return out
 
 
+TIP_WINDOW = 2000
+
+
 @pytest.fixture(scope="module")
 def finger_runs():
+    from paper_1707_00198_amd.lbm import Lattice
     setups = [W.fingering_channel(nx=800, h=50, x_interface=100.0, M=M, theta_deg=th, ca=ca,
                                   nu_r=0.5, sigma=0.05) for M, th, ca in FINGERS]
     out = {}
     for st in ("f64", "f32", "f16", "c16"):
-        fields, m0, m1 = _run(setups, st, FINGER_STEPS)
-        metrics = [finger_metrics(f, s.solid) for f, s in zip(fields, setups)]
+        lat = Lattice(setups, storage=st).step(FINGER_STEPS - TIP_WINDOW)
+        tips = [finger_metrics(_rho_n(lat, d), s.solid)["tip"] for d, s in enumerate(setups)]
+        lat.step(TIP_WINDOW)
+        metrics = [finger_metrics(_rho_n(lat, d), s.solid) for d, s in enumerate(setups)]
+        for m, t0 in zip(metrics, tips):
+            m["tip_velocity"] = (m["tip"] - t0) / TIP_WINDOW
+        del lat
         print(f"[precision] fingers {st}: length = "
-              f"{[round(m['length'], 3) for m in metrics]}", flush=True)
+              f"{[round(m['length'], 3) for m in metrics]}, tip velocity = "
+              f"{[float('%.5g' % m['tip_velocity']) for m in metrics]}", flush=True)
         out[st] = metrics
     return out
 
@@ -87,6 +100,16 @@ def test_finger_length_within_one_percent_of_fp64(finger_runs, storage):
         rel = abs(m["length"] - m64["length"]) / abs(m64["length"])
         assert rel <= 0.01, (f"M={M} theta={th} Ca={ca}: {storage} length {m['length']:.3f} vs "
                              f"f64 {m64['length']:.3f} ({100 * rel:.2f} %)")
+
+
+@pytest.mark.parametrize("storage,bound", [("f32", 0.01), ("c16", 0.01), ("f16", 0.03)])
+def test_tip_velocity_against_fp64(finger_runs, storage, bound):
+    for (M, th, ca), m64, m in zip(FINGERS, finger_runs["f64"], finger_runs[storage]):
+        rel = abs(m["tip_velocity"] - m64["tip_velocity"]) / abs(m64["tip_velocity"])
+        print(f"[precision] {storage} tip velocity M={M} theta={th} Ca={ca}: "
+              f"{m['tip_velocity']:.5g} vs f64 {m64['tip_velocity']:.5g} ({100 * rel:.2f} %)",
+              flush=True)
+        assert rel <= bound
 
 
 def test_binary16_finger_length_error_is_reported(finger_runs):
