@@ -466,9 +466,9 @@ int build_graph(lbm_ctx *c, int parity) {
     if (!c->cap) HIP_OK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     const int p0 = c->parity, own0 = c->own;
     const int64_t s0 = c->steps;
+    HIP_OK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     c->parity = parity;
     c->own = 0;
-    HIP_OK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int k = 0; k < c->graph_steps && e == hipSuccess; k++) e = step_once(c, c->cap);
     hipGraph_t g = nullptr;
