@@ -79,7 +79,9 @@ Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
     L.plane = align_up(std::max<size_t>(nodes, 64), 128);
     L.rows = rows;
     L.items_cap = cap;
-    L.bpd = 16;
+    // mass-reduction blocks per domain: about 4096 blocks in all (16 per CU), so that a single
+    // large domain is not summed by a handful of blocks; 16 to 1024 per domain
+    L.bpd = std::max(16, std::min(1024, (4096 + n - 1) / n));
     const size_t sb = storage_bytes(storage), cb = colour_bytes(storage);
     size_t o = 0;
     for (int b = 0; b < 2; b++) {
