@@ -1,7 +1,7 @@
 """GPU parity: the HIP library against the FP64 oracle, element by element, through the C-ABI.
 
 Bar: FP64 storage matches the oracle's per-colour populations to max-abs 1e-10 (after up to
-1000 steps); reduced precision is judged on physical quantities (contact angle, finger length)
+1000 steps); reduced precision is assessed on physical quantities (contact angle, finger length)
 in test_gpu_precision.py.
 
 Cases are placed off mirror symmetry.  On a mirror axis the estimated colour-gradient direction
