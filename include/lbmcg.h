@@ -20,7 +20,9 @@
  *    Zou-He velocity inlet at x = 0 and a convective outlet at x = nx - 1.
  *  - All device pointers belong to the caller and stay owned by the caller; the library
  *    borrows the state and scratch buffers from lbm_create until lbm_destroy.  The library
- *    itself owns only the context object and host-side tables.
+ *    itself owns only the context object, host-side tables and, once lbm_set_graph turns
+ *    them on, its step graphs and the private stream they are captured on; it allocates no
+ *    device memory.
  *  - Every call returns an lbm_status; nothing throws across this interface.  The text of
  *    the last error on the calling thread is returned by lbm_last_error.
  *  - Work is enqueued on the HIP stream given to lbm_create and is asynchronous unless the
@@ -105,7 +107,10 @@ int lbm_query_bytes(const lbm_domain_desc *domains, int n, int storage, size_t *
  * normals, build the tile schedule and upload everything plus the initial state
  * (f_alpha = rho_k w_alpha, u = 0) into `state_dev` / `scratch_dev` (device pointers of at
  * least the queried sizes, 256-byte aligned).  `hip_stream` is a hipStream_t (NULL = the
- * default stream).  Blocks until the upload has finished.  On success *out owns a context. */
+ * default stream).  Blocks until the upload has finished.  On success *out owns a context.
+ * LBM_EINVAL for an invalid descriptor, NULL or misaligned buffers, or a batch beyond one
+ * context's limit (2^31 bytes for the nine population planes and for the three colour-state
+ * planes); LBM_ENOMEM if a buffer is smaller than lbm_query_bytes reports. */
 int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_dev,
                size_t state_bytes, void *scratch_dev, size_t scratch_bytes, void *hip_stream,
                lbm_ctx **out);
@@ -119,15 +124,17 @@ int lbm_classify(const lbm_domain_desc *domain, uint8_t *classes_out, double *ns
 
 /* Enqueue n_steps time steps of every domain on the context's stream (asynchronous).  With
  * step graphs on (lbm_set_graph), runs of steps go out as replays of an instantiated HIP graph
- * of that many step launches; results are the same bit for bit either way. */
+ * of that many step launches; results are the same bit for bit either way.  LBM_EINVAL for a
+ * negative count; LBM_EDEVICE if a launch (or the first capture of a graph) fails. */
 int lbm_step(lbm_ctx *ctx, int64_t n_steps);
 
 /* Step graphs: `launches` step launches (0 = off, the default, else even, 2..1024) are
  * captured once per starting buffer parity on a private stream of the library and replayed on
  * the context's stream, one graph launch per `launches` steps.  The initial state of a context
  * (node-local, not yet streamed; also after lbm_load_state of such a state) first takes one
- * direct step, and a remainder shorter than a graph is launched step by step.  The graphs are rebuilt after lbm_set_tile and
- * lbm_autotune.  Synchronises the stream.  LBM_EINVAL for an odd or out-of-range count. */
+ * direct step, and a remainder shorter than a graph is launched step by step.  The graphs are
+ * rebuilt after lbm_set_tile and lbm_autotune.  Synchronises the stream.  LBM_EINVAL for an
+ * odd or out-of-range count. */
 int lbm_set_graph(lbm_ctx *ctx, int launches);
 
 /* Autotuner of the step's tile shape on this context's own batch: times every provided shape,
@@ -154,7 +161,8 @@ int lbm_autotune(lbm_ctx *ctx, int steps, void *save_dev, double *out_host);
  * `out_count` doubles): one nx*ny plane per selected quantity, in bit order; solid nodes
  * read 0.  Enqueued on the context's stream.  LBM_ENOMEM if out_count is too small.  The
  * velocity planes are computed by a diagnostic launch of the step (no state is changed) and
- * need an attached diagnostics buffer (LBM_ESTATE otherwise). */
+ * need an attached diagnostics buffer (LBM_ESTATE otherwise).  LBM_EINVAL for an unknown
+ * domain, an empty or unknown field selection, or a NULL output. */
 int lbm_read_fields(lbm_ctx *ctx, int domain, uint32_t which, double *out_dev,
                     size_t out_count);
 
@@ -170,11 +178,15 @@ int64_t lbm_steps_taken(const lbm_ctx *ctx);
  * >= 8; 0 = built-in choice), `waves` tile rows advanced per iteration (4 or 8; 0 = built-in)
  * and `cols` wavefronts side by side in a tile row (1: 64-column tiles with 54 output columns,
  * 2: 128-column tiles with 118; 0 = built-in; 8 x 2 is not provided).  Rebuilds the schedule;
- * results do not depend on the tile shape.  Synchronises the stream. */
+ * results do not depend on the tile shape.  Synchronises the stream.  LBM_EINVAL for a shape
+ * outside these. */
 int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves, int cols);
 
-/* Checkpoint: copy the complete mutable state (state buffer contents plus step parity) to
- * `dst_dev` (device, lbm_state_size bytes) or restore it from `src_dev`.  Stream-ordered. */
+/* Checkpoint: copy the complete mutable state (state buffer contents plus step parity, count
+ * and snapshot mode) to `dst_dev` (device, lbm_state_size bytes) or restore it from `src_dev`.
+ * Both synchronise the stream.  `src_dev` must come from lbm_save_state of a context with the
+ * same domains and storage; lbm_load_state returns LBM_ESTATE if it finds no saved-state header
+ * at the end of the buffer. */
 size_t lbm_state_size(const lbm_ctx *ctx);
 int lbm_save_state(lbm_ctx *ctx, void *dst_dev);
 int lbm_load_state(lbm_ctx *ctx, const void *src_dev);
