@@ -27,6 +27,8 @@
  *    the last error on the calling thread is returned by lbm_last_error.
  *  - Work is enqueued on the HIP stream given to lbm_create and is asynchronous unless the
  *    entry point says otherwise.
+ *  - A context is used by one thread at a time (calls change its step parity, schedule and
+ *    graphs); separate contexts may be driven from separate threads.
  */
 #ifndef LBMCG_H
 #define LBMCG_H
