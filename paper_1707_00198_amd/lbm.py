@@ -254,9 +254,20 @@ class Lattice:
         return out.reshape(-1, 2)
 
     def region_mass(self, dom: int, region) -> np.ndarray:
-        """[rho_R inside, rho_R outside, rho_B inside, rho_B outside] for a (ny, nx) region mask."""
+        """[rho_R inside, rho_R outside, rho_B inside, rho_B outside] for a (ny, nx) region mask:
+        a host array, or a contiguous uint8 tensor already on the device (reused as is)."""
         self._diag()
-        r = self.torch.as_tensor(np.ascontiguousarray(region, dtype=np.uint8), device=self.device)
+        ny, nx = self.setups[dom].solid.shape
+        if isinstance(region, self.torch.Tensor) and region.is_cuda:
+            if region.device != self.device:
+                raise ValueError(f"region is on {region.device}, the lattice on {self.device}")
+            if region.dtype != self.torch.uint8 or not region.is_contiguous() or region.numel() != nx * ny:
+                raise ValueError(f"region must be a contiguous uint8 tensor of {ny} x {nx} elements")
+            r = region
+        else:
+            r = self.torch.as_tensor(np.ascontiguousarray(region, dtype=np.uint8), device=self.device)
+            if r.numel() != nx * ny:
+                raise ValueError(f"region must have {ny} x {nx} elements")
         out = np.empty(4)
         _check(load_library().lbm_diag_region_mass(self._h, dom, r.data_ptr(), _ptr(out, C.c_double)))
         return out

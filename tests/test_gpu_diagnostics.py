@@ -87,6 +87,12 @@ def test_region_mass_matches_oracle():
                      rb[fluid & (region > 0)].sum(), rb[fluid & (region == 0)].sum()])
     print(f"[diag] region masses {got} vs {want}", flush=True)
     assert np.allclose(got, want, rtol=1e-12, atol=1e-12)
+    # the same region handed over as a device tensor is used in place
+    import torch
+    dev = torch.as_tensor(region, device=lat.device)
+    assert np.array_equal(lat.region_mass(0, dev), got)
+    with pytest.raises(ValueError):
+        lat.region_mass(0, dev[:-1])
 
 
 def test_crossings_match_row_crossing():
