@@ -3,7 +3,8 @@
 FP32 storage (FP32 arithmetic) and the 16-bit storages (binary16, and the format with an 11-bit
 fraction, both with per-direction power-of-two scales, FP32 colour state and arithmetic) must
 reproduce the FP64 path's physics:
-  - static contact angle (the Table I flat-wall droplets) within 0.5 degrees;
+  - static contact angle (the Table I flat-wall droplets, and droplets on a cylinder with
+    staircase and analytic wall normals) within 0.5 degrees;
   - finger length of a displacement channel (tip minus contact line) within 1 %.
 The tip velocity over the last 2000 steps of the finger runs is within 1 % of the FP64 one for
 FP32 and c16 storage (measured: 0.00 % and up to 0.26 %); binary16 is reported and bounded at
@@ -82,6 +83,32 @@ def finger_runs():
               f"{[float('%.5g' % m['tip_velocity']) for m in metrics]}", flush=True)
         out[st] = metrics
     return out
+
+
+CYLINDER_THETAS = (30.0, 60.0, 90.0, 120.0)
+CYLINDER_STEPS = 10000
+
+
+@pytest.fixture(scope="module")
+def cylinder_runs():
+    """Droplets on a cylinder (Sec. III B, 200 x 200, R = 40), eighth-order staircase normals and
+    analytic ones, off the mirror axis."""
+    from physics import cylinder_contact_angle
+    setups = [W.cylinder_droplet(theta_deg=t, dcx_offset=0.37, analytic_normals=a, name=f"c{t}{a}")
+              for a in (False, True) for t in CYLINDER_THETAS]
+    out = {}
+    for st in ("f64", "f32", "f16", "c16"):
+        fields, _, _ = _run(setups, st, CYLINDER_STEPS)
+        out[st] = [cylinder_contact_angle(f, s.solid, s.meta["ccx"], s.meta["ccy"], s.meta["rc"])[0]
+                   for f, s in zip(fields, setups)]
+        print(f"[precision] cylinders {st}: theta = {np.round(out[st], 3).tolist()}", flush=True)
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "c16"])
+def test_curved_wall_contact_angle_within_half_degree_of_fp64(cylinder_runs, storage):
+    d = np.abs(np.array(cylinder_runs[storage]) - np.array(cylinder_runs["f64"]))
+    assert d.max() <= 0.5, (storage, d)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "c16"])
