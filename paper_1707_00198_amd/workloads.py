@@ -300,3 +300,48 @@ def cfg_wetting_batch(n_cyl=128, n_cap=64, seed=SEED + 1):
                              blue_x0=600, blue_x1=1875, theta_deg=float(thetas[k % 4]),
                              M=float(Ms[(k // 4) % 4]), nu_r=0.1, sigma=0.05))
     return out
+
+
+CONFIGS = {
+    "droplet": lambda: [cfg_droplet_flat()],
+    "fingering": lambda: [cfg_fingering()],
+    "fingering_large": lambda: [cfg_fingering_large()],
+    "sweep": cfg_sweep,
+    "wetting_batch": cfg_wetting_batch,
+    "x8": cfg_x8,
+    "x9": cfg_x9,
+}
+
+
+def describe(setups) -> dict:
+    """JSON-ready description of a batch: per domain its extent, fluid nodes, boundary kind,
+    wetting flags, physical parameters and the set-up's own metadata (the seeded geometry is
+    rebuilt from the generator; the arrays themselves are not written)."""
+    def plain(v):
+        if isinstance(v, (np.floating, np.integer)):
+            return v.item()
+        if isinstance(v, (list, tuple)):
+            return [plain(x) for x in v]
+        return v
+    doms = []
+    for s in setups:
+        doms.append(dict(name=s.name, nx=s.nx, ny=s.ny, fluid_nodes=s.fluid_nodes,
+                         open_x=bool(s.open_x), analytic_normals=s.ns is not None,
+                         wetting=int(s.wetting), params={k: plain(v) for k, v in s.params.items()},
+                         meta={k: plain(v) for k, v in s.meta.items()}))
+    return dict(seed=SEED, domains=len(doms), fluid_nodes=sum(d["fluid_nodes"] for d in doms),
+                domain_list=doms)
+
+
+def main(argv=None) -> None:
+    """``python -m paper_1707_00198_amd.workloads <config>`` prints the configuration as JSON."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("config", choices=sorted(CONFIGS))
+    args = ap.parse_args(argv)
+    print(json.dumps(describe(CONFIGS[args.config]()), indent=1))
+
+
+if __name__ == "__main__":
+    main()
