@@ -95,13 +95,11 @@ def time_lattice(setups, storage, steps, warmup, chunk_rows=0, autotune=False):
     import torch
     from paper_1707_00198_amd.lbm import Lattice
     lat = Lattice(setups, storage=storage)
-    tile = "built-in rule"
     if chunk_rows:
         lat.set_tile(chunk_rows)
-        tile = {"chunk_rows": chunk_rows}
     if autotune:
-        tile = lat.autotune(steps=10)
-        print(f"[bench] autotuned tile: {tile}", flush=True)
+        print(f"[bench] autotuned tile: {lat.autotune(steps=10)}", flush=True)
+    tile = dict(lat.tile, rule="autotuned" if autotune else ("set" if chunk_rows else "built-in"))
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()

@@ -184,6 +184,11 @@ int64_t lbm_steps_taken(const lbm_ctx *ctx);
  * outside these. */
 int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves, int cols);
 
+/* The tile shape in use (the built-in choice, lbm_set_tile's or lbm_autotune's): shape_out
+ * (host, 4 ints) receives chunk_rows, waves, cols and the number of work items, i.e. blocks
+ * per step launch.  Host-only.  LBM_EINVAL for a NULL argument. */
+int lbm_get_tile(const lbm_ctx *ctx, int *shape_out);
+
 /* Checkpoint: copy the complete mutable state (state buffer contents plus step parity, count
  * and snapshot mode) to `dst_dev` (device, lbm_state_size bytes) or restore it from `src_dev`.
  * Both synchronise the stream.  `src_dev` must come from lbm_save_state of a context with the

@@ -848,6 +848,15 @@ int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves, int cols) {
     return upload_items(c);
 }
 
+int lbm_get_tile(const lbm_ctx *c, int *shape_out) {
+    if (!c || !shape_out) return fail(LBM_EINVAL, "null argument");
+    shape_out[0] = c->chunk_rows;
+    shape_out[1] = c->waves;
+    shape_out[2] = c->cols;
+    shape_out[3] = (int)c->items.size();
+    return LBM_OK;
+}
+
 size_t lbm_state_size(const lbm_ctx *c) { return c ? c->L.state_bytes + 256 : 0; }
 
 int lbm_save_state(lbm_ctx *c, void *dst_dev) {

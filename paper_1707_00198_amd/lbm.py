@@ -55,6 +55,7 @@ PROTOTYPES = {
     "lbm_mass": (C.c_int, [C.c_void_p, _dp]),
     "lbm_steps_taken": (C.c_int64, [C.c_void_p]),
     "lbm_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "lbm_get_tile": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
     "lbm_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
     "lbm_state_size": (C.c_size_t, [C.c_void_p]),
@@ -182,6 +183,13 @@ class Lattice:
 
     def set_tile(self, chunk_rows: int = 0, waves: int = 0, cols: int = 0):
         _check(load_library().lbm_set_tile(self._h, int(chunk_rows), int(waves), int(cols)))
+
+    @property
+    def tile(self) -> dict:
+        """The step's tile shape in use and its work items (blocks per launch)."""
+        out = (C.c_int * 4)()
+        _check(load_library().lbm_get_tile(self._h, out))
+        return dict(chunk_rows=out[0], waves=out[1], cols=out[2], items=out[3])
 
     def set_graph(self, launches: int):
         """Replay runs of `launches` steps (even; 0 = off) as one HIP graph launch each."""

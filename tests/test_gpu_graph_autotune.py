@@ -95,6 +95,9 @@ def test_autotune_keeps_the_state_and_picks_an_offered_shape(storage):
     assert info["chunk_rows"] in (8, 12, 16, 24, 32, 48, 64)
     assert (info["waves"], info["cols"]) in ((4, 1), (8, 1), (4, 2))
     assert info["ms_per_step"] > 0.0
+    assert {k: lat.tile[k] for k in ("chunk_rows", "waves", "cols")} == \
+        {k: info[k] for k in ("chunk_rows", "waves", "cols")}
+    assert lat.tile["items"] > 0
     lat.set_graph(6)  # the tuned shape under replays too
     lat.step(37)
     ref.step(37)

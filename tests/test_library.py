@@ -107,6 +107,8 @@ def test_wetting_flags_validated():
 def test_graph_and_autotune_reject_null_arguments():
     L = lbm.load_library()
     assert L.lbm_set_graph(None, 8) == -1 and "null context" in L.lbm_last_error().decode()
+    shape = (C.c_int * 4)()
+    assert L.lbm_get_tile(None, shape) == -1 and "null" in L.lbm_last_error().decode()
     out = (C.c_double * 4)()
     assert L.lbm_autotune(None, 5, None, out) == -1 and "null" in L.lbm_last_error().decode()
 
