@@ -56,7 +56,10 @@ typedef enum {
  * power-of-two scale per direction (2^9 rest, 2^11 axis, 2^13 diagonal): LBM_STORE_F16 stores
  * binary16, LBM_STORE_C16 a format with one more significand bit (sign, 4-bit exponent with
  * bias 7, 11-bit fraction, subnormals; relative rounding error below 2^-12, saturating beyond
- * |deviation| = 2.25 w_alpha rho0).  Colour state is FP64 / FP32. */
+ * |deviation| = 2.25 w_alpha rho0).  Colour state is FP64 / FP32.
+ * Accuracy against FP64 storage on displacement channels: FP32 and LBM_STORE_C16 keep the finger
+ * length within 1 %; LBM_STORE_F16 does not (measured 0.7-1.6 % short, tip velocity up to 2 %),
+ * so runs held to a 1 % finger-length bar should use LBM_STORE_C16. */
 typedef enum {
     LBM_STORE_F64 = 0,
     LBM_STORE_F32 = 1,
@@ -108,7 +111,8 @@ int lbm_query_bytes(const lbm_domain_desc *domains, int n, int storage, size_t *
 /* Validate, classify nodes (fluid, outermost fluid, outermost solid, solid), compute wall
  * normals, build the tile schedule and upload everything plus the initial state
  * (f_alpha = rho_k w_alpha, u = 0) into `state_dev` / `scratch_dev` (device pointers of at
- * least the queried sizes, 256-byte aligned).  `hip_stream` is a hipStream_t (NULL = the
+ * least the queried sizes, 256-byte aligned) of the device current during the call, which
+ * becomes the context's device.  `hip_stream` is a hipStream_t of that device (NULL = the
  * default stream).  Blocks until the upload has finished.  On success *out owns a context.
  * LBM_EINVAL for an invalid descriptor, NULL or misaligned buffers, or a batch beyond one
  * context's limit (2^31 bytes for the nine population planes and for the three colour-state
@@ -141,13 +145,14 @@ int lbm_set_graph(lbm_ctx *ctx, int launches);
 
 /* Autotuner of the step's tile shape on this context's own batch: times every provided shape,
  * chunk_rows in {8, 12, 16, 24, 32, 48, 64} (shapes that cut no domain differently are timed
- * once) x (waves, cols) in {(4, 1), (8, 1), (4, 2)}, with `steps` (1..100000) timed steps after
- * one untimed step each, re-times the three fastest and keeps the fastest (as lbm_set_tile).
- * The trials run real steps, so the state is first saved to `save_dev` (caller-owned device
- * buffer of lbm_state_size bytes) and restored afterwards: the state, the step count and the
- * non-finite flag are as before the call, and results never depend on the tile shape.  If
- * `out_host` is not NULL it receives (chunk_rows, waves, cols, milliseconds per step) of the
- * choice.  Synchronises the stream.  On LBM_EDEVICE the state is undefined. */
+ * once) x (waves, cols, cols_per_lane) in {(4, 1, 1), (8, 1, 1), (4, 2, 1)}, plus (4, 1, 2) and
+ * (8, 1, 2) where lbm_set_tile allows two columns per lane, with `steps` (1..100000) timed steps
+ * after one untimed step each, re-times the three fastest and keeps the fastest (as
+ * lbm_set_tile).  The trials run real steps, so the state is first saved to `save_dev`
+ * (caller-owned device buffer of lbm_state_size bytes) and restored afterwards: the state, the
+ * step count and the non-finite flag are as before the call.  If `out_host` is not NULL it
+ * receives (chunk_rows, waves, cols, milliseconds per step, cols_per_lane) of the choice.
+ * Synchronises the stream.  On LBM_EDEVICE the state is undefined. */
 int lbm_autotune(lbm_ctx *ctx, int steps, void *save_dev, double *out_host);
 
 /* Field selection bits for lbm_read_fields. */
@@ -177,16 +182,22 @@ int lbm_mass(lbm_ctx *ctx, double *out_host);
 int64_t lbm_steps_taken(const lbm_ctx *ctx);
 
 /* Tile shape of the fused step: `chunk_rows` rows of a strip per work item (multiple of 4,
- * >= 8; 0 = built-in choice), `waves` tile rows advanced per iteration (4 or 8; 0 = built-in)
- * and `cols` wavefronts side by side in a tile row (1: 64-column tiles with 54 output columns,
- * 2: 128-column tiles with 118; 0 = built-in; 8 x 2 is not provided).  Rebuilds the schedule;
- * results do not depend on the tile shape.  Synchronises the stream.  LBM_EINVAL for a shape
- * outside these. */
-int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves, int cols);
+ * >= 8; 0 = built-in choice), `waves` tile rows advanced per iteration (4 or 8; 0 = built-in),
+ * `cols` wavefronts side by side in a tile row and `cols_per_lane` node columns per lane:
+ *   cols 1, cols_per_lane 1: 64-column tiles with 54 output columns;
+ *   cols 2, cols_per_lane 1: 128-column tiles with 118 output columns (8 x 2 not provided);
+ *   cols 1, cols_per_lane 2: 128-column tiles with 116 output columns, each lane updating two
+ *     adjacent nodes; only for the FP32-arithmetic storages and batches whose domains all have an
+ *     even nx (never the built-in choice; lbm_autotune weighs it).
+ * 0 selects the built-in value.  Rebuilds the schedule.  Every shape computes the same method
+ * with the same per-node arithmetic (FP64: the same bits; FP32 arithmetic: each shape is checked
+ * against the FP64 oracle to the storage's rounding).  Synchronises the stream.  LBM_EINVAL for a
+ * shape outside these. */
+int lbm_set_tile(lbm_ctx *ctx, int chunk_rows, int waves, int cols, int cols_per_lane);
 
 /* The tile shape in use (the built-in choice, lbm_set_tile's or lbm_autotune's): shape_out
- * (host, 4 ints) receives chunk_rows, waves, cols and the number of work items, i.e. blocks
- * per step launch.  Host-only.  LBM_EINVAL for a NULL argument. */
+ * (host, 5 ints) receives chunk_rows, waves, cols, the number of work items (blocks per step
+ * launch) and cols_per_lane.  Host-only.  LBM_EINVAL for a NULL argument. */
 int lbm_get_tile(const lbm_ctx *ctx, int *shape_out);
 
 /* Checkpoint: copy the complete mutable state (state buffer contents plus step parity, count

@@ -64,8 +64,8 @@ struct Layout {
            mass_out = 0, flag = 0, scratch_bytes = 0;
 };
 
-int strips_of(const lbm_domain_desc &d, int cols = 1) {
-    return (d.nx + tile_out(cols) - 1) / tile_out(cols);
+int strips_of(const lbm_domain_desc &d, int cols = 1, int npl = 1) {
+    return (d.nx + tile_out(cols, npl) - 1) / tile_out(cols, npl);
 }
 
 Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
@@ -255,6 +255,7 @@ struct lbm_ctx {
     int chunk_rows = 0;
     int waves = 0;    // wavefronts (tile rows advanced per iteration) of the step kernel
     int cols = 1;     // wavefronts side by side in a tile row (tile width 64 cols)
+    int npl = 1;      // node columns per lane: 1, or 2 (pair kernel; tile width 128, cols = 1)
     bool variants = false;  // some domain uses a wetting variant (LBM_WET_*)
     int parity = 0;   // buffer holding the current state
     int own = 1;      // current state is a node-local snapshot
@@ -384,17 +385,17 @@ AnyArgs make_diag_args(const lbm_ctx *c, int cl_dom = -1) {
 // stream a narrow band of every plane, which measured markedly faster than a strip at a time.
 // A domain with more items than one run is cut into strip groups of about one run each, so
 // that every XCD works through a compact region and neighbouring strips share its L2.
-std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk, int cols) {
+std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk, int cols, int npl) {
     size_t total = 0;
     for (const auto &q : d) {
         const int nch = std::max(1, (q.ny + chunk - 1) / chunk);
-        total += (size_t)strips_of(q, cols) * nch;
+        total += (size_t)strips_of(q, cols, npl) * nch;
     }
     const size_t run = std::max<size_t>(1, total / 8);
     std::vector<WorkItem> out;
     out.reserve(total);
     for (int i = 0; i < (int)d.size(); i++) {
-        const int ny = d[i].ny, S = strips_of(d[i], cols);
+        const int ny = d[i].ny, S = strips_of(d[i], cols, npl);
         const int nch = std::max(1, (ny + chunk - 1) / chunk);
         const int ch = ((ny + nch - 1) / nch + 3) / 4 * 4;
         const size_t items = (size_t)S * nch;
@@ -404,7 +405,7 @@ std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chu
             for (int k = 0; k < nch; k++) {
                 const int y0 = k * ch, y1 = std::min(ny, y0 + ch);
                 if (y0 >= y1) continue;
-                for (int s = s0; s < s1; s++) out.push_back(WorkItem{i, s * tile_out(cols), y0, y1});
+                for (int s = s0; s < s1; s++) out.push_back(WorkItem{i, s * tile_out(cols, npl), y0, y1});
             }
         }
     }
@@ -418,11 +419,11 @@ std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chu
 // (15 or 44 of 630 x 60) ran 15-23 % faster in 16-row chunks than in 8-row ones, whose halo
 // rows double the work, while a single 2000 x 100 channel (266 items at 16 rows) ran fastest
 // in 8-row chunks, where more items outweigh the halo.
-int auto_chunk(const std::vector<lbm_domain_desc> &d, int cols) {
+int auto_chunk(const std::vector<lbm_domain_desc> &d, int cols, int npl) {
     for (int ch : {64, 48, 32, 24})
-        if (build_items(d, ch, cols).size() >= 4096) return ch;
+        if (build_items(d, ch, cols, npl).size() >= 4096) return ch;
     for (int ch : {16, 12})
-        if (build_items(d, ch, cols).size() >= 512) return ch;
+        if (build_items(d, ch, cols, npl).size() >= 512) return ch;
     return 8;
 }
 
@@ -432,6 +433,17 @@ int default_waves(int) { return 4; }
 // One-wavefront tiles.  Tiles two wavefronts wide (118 output columns of 128) repeat fewer
 // halo columns but measured 3-5 % slower on the sweep (8-wavefront barriers, 2 blocks per CU).
 int default_cols(int) { return 1; }
+// The pair kernel (two node columns per lane) needs FP32 arithmetic and an even width in every
+// domain.  It is offered to lbm_set_tile and the autotuner but is not the built-in choice: at the
+// two wavefronts per SIMD its register use allows, it measured slower than the one-column kernel
+// at four (sweep 33.4 against 47.8 GLUPS).
+bool pair_allowed(int storage, const std::vector<lbm_domain_desc> &d) {
+    if (storage == 0) return false;
+    for (const auto &q : d)
+        if (q.nx % 2) return false;
+    return true;
+}
+int default_npl(int, const std::vector<lbm_domain_desc> &) { return 1; }
 
 int upload_items(lbm_ctx *c) {
     if (c->items.size() > c->L.items_cap) return fail(LBM_EINVAL, "work-item table overflow");
@@ -444,7 +456,7 @@ int upload_items(lbm_ctx *c) {
 // One step launched directly on stream s, with the context's current arguments.
 hipError_t step_once(lbm_ctx *c, hipStream_t s) {
     AnyArgs a = make_args(c, c->parity);
-    const hipError_t e = launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->cols,
+    const hipError_t e = launch_step(c->storage, a.bytes, (int)c->items.size(), c->waves, c->cols, c->npl,
                                      c->variants, s);
     if (e != hipSuccess) return e;
     c->parity ^= 1;
@@ -621,9 +633,10 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     c->desc.assign(domains, domains + n);
     c->doms.resize(n);
     c->waves = default_waves(storage);
+    c->npl = default_npl(storage, c->desc);
     c->cols = default_cols(storage);
-    c->chunk_rows = auto_chunk(c->desc, c->cols);
-    c->items = build_items(c->desc, c->chunk_rows, c->cols);
+    c->chunk_rows = auto_chunk(c->desc, c->cols, c->npl);
+    c->items = build_items(c->desc, c->chunk_rows, c->cols, c->npl);
     if (hipHostMalloc((void **)&c->mass_host, (2 * (size_t)n + 2) * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->flag_host, 64) != hipSuccess) {
         delete c;
@@ -703,22 +716,25 @@ int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
     HIP_OK(hipStreamSynchronize(c->stream));
     const int flag0 = *c->flag_host;
     struct Trial {
-        int chunk, waves, cols;
+        int chunk, waves, cols, npl;
         double ms;
     };
     std::vector<Trial> trials;
-    const int shapes[3][2] = {{4, 1}, {8, 1}, {4, 2}};  // (waves, cols)
+    // (waves, cols, node columns per lane); the pair-kernel shapes where the batch allows them
+    const int shapes[5][3] = {{4, 1, 1}, {8, 1, 1}, {4, 2, 1}, {4, 1, 2}, {8, 1, 2}};
+    const bool pairs = pair_allowed(c->storage, c->desc);
     for (const auto &sh : shapes) {
+        if (sh[2] == 2 && !pairs) continue;
         std::vector<WorkItem> prev;
         for (int ch : {8, 12, 16, 24, 32, 48, 64}) {
-            std::vector<WorkItem> it = build_items(c->desc, ch, sh[1]);
+            std::vector<WorkItem> it = build_items(c->desc, ch, sh[1], sh[2]);
             // a taller chunk that cuts no domain differently is the same schedule
             if (it.size() == prev.size() &&
                 std::equal(it.begin(), it.end(), prev.begin(), [](const WorkItem &a, const WorkItem &b) {
                     return a.dom == b.dom && a.x0 == b.x0 && a.y0 == b.y0 && a.y1 == b.y1;
                 }))
                 continue;
-            trials.push_back({ch, sh[0], sh[1], 0.0});
+            trials.push_back({ch, sh[0], sh[1], sh[2], 0.0});
             prev.swap(it);
         }
     }
@@ -733,7 +749,8 @@ int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
         c->chunk_rows = t.chunk;
         c->waves = t.waves;
         c->cols = t.cols;
-        c->items = build_items(c->desc, t.chunk, t.cols);
+        c->npl = t.npl;
+        c->items = build_items(c->desc, t.chunk, t.cols, t.npl);
         if (upload_items(c)) return hipErrorInvalidValue;
         hipError_t e = step_once(c, c->stream);
         if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
@@ -764,7 +781,8 @@ int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
     c->chunk_rows = best.chunk;
     c->waves = best.waves;
     c->cols = best.cols;
-    c->items = build_items(c->desc, best.chunk, best.cols);
+    c->npl = best.npl;
+    c->items = build_items(c->desc, best.chunk, best.cols, best.npl);
     rc = upload_items(c);
     if (rc) return rc;
     drop_graphs(c);
@@ -779,6 +797,7 @@ int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
         out_host[1] = best.waves;
         out_host[2] = best.cols;
         out_host[3] = best.ms / 2.0;  // mean of the two timings
+        out_host[4] = best.npl;
     }
     return LBM_OK;
 }
@@ -804,7 +823,7 @@ int lbm_read_fields(lbm_ctx *c, int domain, uint32_t which, double *out_dev, siz
     }
     if (which & 24u) {
         AnyArgs da = make_diag_args(c);
-        HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
+        HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->npl, c->variants, c->stream));
         double *ox = (which & 8u) ? out_dev + (p++) * nn : nullptr;
         double *oy = (which & 16u) ? out_dev + p * nn : nullptr;
         HIP_OK(launch_velocity_copy(c->storage, a.bytes, domain, c->diag + diag_layout(c).u, ox, oy,
@@ -831,20 +850,29 @@ int lbm_mass(lbm_ctx *c, double *out_host) {
 
 int64_t lbm_steps_taken(const lbm_ctx *c) { return c ? c->steps : -1; }
 
-int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves, int cols) {
+int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves, int cols, int cols_per_lane) {
     if (!c) return fail(LBM_EINVAL, "null context");
     if (chunk_rows != 0 && (chunk_rows < 8 || chunk_rows % 4))
         return fail(LBM_EINVAL, "chunk rows must be 0 or a multiple of 4 >= 8");
     if (waves != 0 && waves != 4 && waves != 8) return fail(LBM_EINVAL, "waves must be 0, 4 or 8");
     if (cols != 0 && cols != 1 && cols != 2) return fail(LBM_EINVAL, "cols must be 0, 1 or 2");
-    const int w = waves ? waves : default_waves(c->storage), k = cols ? cols : default_cols(c->storage);
+    if (cols_per_lane != 0 && cols_per_lane != 1 && cols_per_lane != 2)
+        return fail(LBM_EINVAL, "cols_per_lane must be 0, 1 or 2");
+    const int w = waves ? waves : default_waves(c->storage);
+    int npl = cols_per_lane;
+    if (npl == 0) npl = cols == 2 ? 1 : default_npl(c->storage, c->desc);
+    const int k = cols ? cols : default_cols(c->storage);
     if (w == 8 && k == 2) return fail(LBM_EINVAL, "tiles of 8 x 2 wavefronts are not provided");
+    if (npl == 2 && k != 1) return fail(LBM_EINVAL, "two columns per lane need one wavefront per tile row");
+    if (npl == 2 && !pair_allowed(c->storage, c->desc))
+        return fail(LBM_EINVAL, "two columns per lane need FP32 arithmetic and an even nx in every domain");
     HIP_OK(hipStreamSynchronize(c->stream));
     drop_graphs(c);
     c->waves = w;
     c->cols = k;
-    c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc, c->cols);
-    c->items = build_items(c->desc, c->chunk_rows, c->cols);
+    c->npl = npl;
+    c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc, c->cols, c->npl);
+    c->items = build_items(c->desc, c->chunk_rows, c->cols, c->npl);
     return upload_items(c);
 }
 
@@ -854,6 +882,7 @@ int lbm_get_tile(const lbm_ctx *c, int *shape_out) {
     shape_out[1] = c->waves;
     shape_out[2] = c->cols;
     shape_out[3] = (int)c->items.size();
+    shape_out[4] = c->npl;
     return LBM_OK;
 }
 
@@ -915,7 +944,7 @@ int lbm_diag_velocity(lbm_ctx *c, int snapshot, double *out_host) {
     if (!c->diag) return fail(LBM_ESTATE, "no diagnostics buffer attached (lbm_diag_attach)");
     const DiagLayout DL = diag_layout(c);
     AnyArgs da = make_diag_args(c);
-    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
+    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->npl, c->variants, c->stream));
     double *res = reinterpret_cast<double *>(c->diag + DL.res);
     HIP_OK(launch_velocity_stats(c->storage, da.bytes, c->n, c->diag + DL.u,
                                  c->snap_valid ? c->diag + DL.snap : nullptr,
@@ -979,7 +1008,7 @@ int lbm_diag_contact_line(lbm_ctx *c, int domain, int32_t *out_host, int cap, in
     int *dcount = reinterpret_cast<int *>(c->diag + DL.cl_count);
     HIP_OK(hipMemsetAsync(dcount, 0, sizeof(int), c->stream));
     AnyArgs da = make_diag_args(c, domain);
-    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->variants, c->stream));
+    HIP_OK(launch_step(c->storage, da.bytes, (int)c->items.size(), c->waves, c->cols, c->npl, c->variants, c->stream));
     HIP_OK(hipMemcpyAsync(c->rows_host, dcount, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     const int n = c->rows_host[0];

@@ -18,7 +18,11 @@ constexpr int TILE_LANES = 64;     // columns per tile row (one wavefront)
 constexpr int HALO = 5;            // halo columns per side: the step's dependency radius next to
                                    // walls is 4, plus one column for the colour-state stencil
 constexpr int TILE_OUT = TILE_LANES - 2 * HALO;  // output columns of a one-wavefront-wide tile
-inline int tile_out(int cols) { return TILE_LANES * cols - 2 * HALO; }
+// Output columns of a tile: `cols` wavefronts side by side with one column per lane (halo 5 on
+// each side), or one wavefront with two columns per lane (npl = 2: 128 columns, halo 6).
+inline int tile_out(int cols, int npl = 1) {
+    return npl == 2 ? 2 * TILE_LANES - 12 : TILE_LANES * cols - 2 * HALO;
+}
 
 // Per-domain parameters in one arithmetic type, with the constant factors of the collision
 // precomputed: ke = 6 (1 - s_e / 2), keps = 6 (1 - s_eps / 2), kq = 1 - s_q / 2 (the forcing
@@ -98,8 +102,10 @@ struct StepArgs {
 
 // Launchers (lbm_kernels.hip).  storage: 0 f64, 1 f32, 2 f16, 3 c16.
 // waves x cols wavefronts per block: (4, 1), (8, 1) or (4, 2); a tile is 64 cols columns wide.
+// npl: node columns per lane, 1, or 2 (the pair kernel: FP32-arithmetic storages, cols = 1,
+// every domain of even width; the tile is then 128 columns wide).
 // variants: some domain has nonzero wetting flags (selects the kernel that tests them).
-hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols,
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols, int npl,
                        bool variants, hipStream_t s);
 hipError_t launch_read(int storage, const void *args, int dom, int nx, int ny, uint32_t which,
                        double *out, hipStream_t s);

@@ -979,6 +979,588 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     }
 }
 
+// --------------------------------------------------- the step kernel with two columns per lane
+// Same method, same stages and the same per-node arithmetic as step_kernel, for the storages
+// with FP32 arithmetic, but each lane owns two adjacent node columns (an even one and the next)
+// of a window 128 columns wide: one wavefront per tile row, 116 output columns and a halo of 6
+// on each side (even, so that a lane's two columns are both output or both halo).  Two nodes per
+// lane halve the share of halo lanes and of per-lane row overhead (addresses, loop control, ring
+// slots), and every population, colour-state and class-word access moves both nodes at once:
+// one 4-byte access per 16-bit population pair (8 bytes for FP32), so each vector memory
+// instruction carries twice the bytes.  Requires an even nx in every domain (the host falls back
+// to step_kernel otherwise), so that a lane's pair never straddles a row end or a periodic seam.
+//
+// Pulls read the pair (x - e_x, x + 1 - e_x) of row y - e_y in one access; for e_x != 0 that is a
+// 2-byte aligned 4-byte access (unaligned global access mode).  Where the two nodes of a lane need
+// non-adjacent sources - one of them bounces back from a solid node and the other does not, or the
+// pull crosses a periodic seam - the pair access serves the even node and the odd node's value is
+// loaded on its own in stage A (rare: curved walls and seam columns; straight walls bounce both).
+template <class T>
+struct PairIO;
+template <>
+struct PairIO<C16> {
+    using V = uint32_t;
+    __device__ static V load(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+    }
+    __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, V v) {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, vo, so, 0);
+    }
+    // Sign and 15 exponent-and-fraction bits of each half moved to bits 31 and 12..26 of an FP32
+    // word (the same word Codec<C16>::decode forms), by one arithmetic shift and one mask each.
+    __device__ static void decode(V v, int a, float &lo, float &hi) {
+        const uint32_t l = (uint32_t)((int32_t)(v << 16) >> 4) & 0x87FFF000u;
+        const uint32_t h = (uint32_t)((int32_t)v >> 4) & 0x87FFF000u;
+        lo = __uint_as_float(l) * Codec<C16>::dec(a);
+        hi = __uint_as_float(h) * Codec<C16>::dec(a);
+    }
+    __device__ static V encode(float lo, float hi, int a) {
+        return (uint32_t)Codec<C16>::encode(lo, a).bits | ((uint32_t)Codec<C16>::encode(hi, a).bits << 16);
+    }
+    __device__ static V zero() { return 0u; }
+};
+template <>
+struct PairIO<__half> {
+    using V = uint32_t;
+    __device__ static V load(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+    }
+    __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, V v) {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, vo, so, 0);
+    }
+    __device__ static void decode(V v, int a, float &lo, float &hi) {
+        lo = Codec<__half>::decode(__ushort_as_half((unsigned short)(v & 0xFFFFu)), a);
+        hi = Codec<__half>::decode(__ushort_as_half((unsigned short)(v >> 16)), a);
+    }
+    __device__ static V encode(float lo, float hi, int a) {
+        return (uint32_t)__half_as_ushort(Codec<__half>::encode(lo, a)) |
+               ((uint32_t)__half_as_ushort(Codec<__half>::encode(hi, a)) << 16);
+    }
+    __device__ static V zero() { return 0u; }
+};
+template <>
+struct PairIO<float> {
+    using V = Pair<float>;
+    __device__ static V load(Rsrc r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, V v) {
+        using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, 0);
+    }
+    __device__ static void decode(V v, int, float &lo, float &hi) {
+        lo = v.x;
+        hi = v.y;
+    }
+    __device__ static V encode(float lo, float hi, int) { return V{lo, hi}; }
+    __device__ static V zero() { return V{0.0f, 0.0f}; }
+};
+
+__device__ __forceinline__ Pair<float> load_f2(Rsrc r, uint32_t vo, uint32_t so) {
+    return __builtin_bit_cast(Pair<float>, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+__device__ __forceinline__ void store_f2(Rsrc r, uint32_t vo, uint32_t so, float lo, float hi) {
+    using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, Pair<float>{lo, hi}), r, vo, so, 0);
+}
+struct Quad {
+    float a, b, c, d;
+};
+__device__ __forceinline__ Quad load_f4(Rsrc r, uint32_t vo) {
+    return __builtin_bit_cast(Quad, __builtin_amdgcn_raw_buffer_load_b128(r, vo, 0, 0));
+}
+
+// Element (plane * plane_elems + node) that node (x, y) with neighbourhood nb and class word m
+// needs for direction a: the pull source x - e_a in plane a, the node's own value in plane
+// opp(a) for a link from a solid node (half-way bounce-back), the node itself in snapshot mode;
+// -1 for a pull across the inlet or the outlet (completed by the boundary condition).
+__device__ __forceinline__ long long pull_elem(const Nbr &nb, int x, uint32_t m, int a, bool own,
+                                               size_t plane_elems) {
+    const size_t self = nb.row[1] + x;
+    if (own || a == 0) return (long long)(a * plane_elems + self);
+    if (pull_outside(nb, a)) return -1;
+    if (m & (1u << (OPP[a] - 1))) return (long long)(OPP[a] * plane_elems + self);
+    return (long long)(a * plane_elems + pull_src(nb, a));
+}
+
+constexpr int PAIR_HALO = 6;                          // halo columns per side (even)
+constexpr int PAIR_COLS = 2 * TILE_LANES;             // window columns
+constexpr int PAIR_OUT = PAIR_COLS - 2 * PAIR_HALO;   // output columns of a window
+
+template <class T, int R, bool WV>
+__global__ __launch_bounds__(TILE_LANES *R, 2) void pair_kernel(const StepArgs<T, float> A) {
+    using AT = float;
+    using IO = PairIO<T>;
+    using PV = typename IO::V;
+    constexpr int Q = 2 * R;
+    constexpr int TW = PAIR_COLS;
+    constexpr uint32_t SB = sizeof(T), CB = sizeof(AT);
+    __shared__ AT s_rn[Q][TW];
+    __shared__ AT s_nx[Q][TW], s_ny[Q][TW];
+    __shared__ AT s_gx[Q][TW], s_gy[Q][TW];
+    __shared__ AT s_c[Q][TW], s_vx[Q][TW], s_vy[Q][TW];
+    __shared__ AT s_wx[Q][TW], s_wy[Q][TW];
+    __shared__ uint16_t s_m[Q][TW];
+    __shared__ int s_wall[Q];
+
+    const WorkItem *itp = A.items + item_of_block(blockIdx.x, A.n_items);
+    const int dom = __builtin_amdgcn_readfirstlane(itp->dom);
+    const int x0 = __builtin_amdgcn_readfirstlane(itp->x0);
+    const int y0 = __builtin_amdgcn_readfirstlane(itp->y0), y1 = __builtin_amdgcn_readfirstlane(itp->y1);
+    DomC &D = *(DomC *)(A.doms + dom);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / TILE_LANES);
+    const int lane = threadIdx.x % TILE_LANES;
+    const int base = x0 - PAIR_HALO;
+    // the lane's two window columns and node columns (periodic, or clamped at an open x axis)
+    int col[2], X[2], xe[2], edge_col[2];
+    bool out[2], gath[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        col[k] = 2 * lane + k;
+        X[k] = base + col[k];
+        xe[k] = D.open_x ? min(max(X[k], 0), D.nx - 1) : wrap(X[k], D.nx);
+        edge_col[k] = xe[k] != X[k] && D.open_x ? xe[k] - base : -1;
+        out[k] = col[k] >= PAIR_HALO && col[k] < TW - PAIR_HALO && X[k] < D.nx;
+        // columns beyond an open end take the edge column's stencil values (replicate below),
+        // so they gather nothing themselves
+        gath[k] = col[k] >= 1 && col[k] < TW - 1 && edge_col[k] < 0;
+    }
+    // the window reaches past a domain edge (an open end or a periodic seam)
+    const bool edge_item = base < 0 || base + TW > D.nx;
+    const bool open_edge = D.open_x && edge_item;
+    ParC<AT> &P = par(D, AT());
+    const AT eps = P.eps;
+    const bool rec_cl = A.diag && A.cl_count != nullptr && dom == A.cl_dom;
+    const bool scheme_b = WV && (D.wetting & WET_SCHEME_B);
+    const bool surface_energy = WV && (D.wetting & WET_SURFACE_ENERGY);
+    const int r_first = y0 - HALO + 1 - R;
+
+    const Rsrc f_in = make_rsrc(A.fin, A.f_set_bytes), f_out = make_rsrc(A.fout, A.diag ? 0u : A.f_set_bytes);
+    const Rsrc c_in = make_rsrc(A.cin, 3 * A.c_plane_bytes);
+    const Rsrc c_out = A.diag ? make_rsrc(A.u_out, 2 * A.c_plane_bytes) : make_rsrc(A.cout, 3 * A.c_plane_bytes);
+    const Rsrc r_mask = make_rsrc(A.mask, (uint32_t)A.plane * 2u);
+    const Rsrc r_ns = make_rsrc(A.ns, A.ns_bytes);
+    const uint32_t FP = A.f_plane_bytes, CP = A.c_plane_bytes;
+
+    auto row_ok_a = [&](int y) { return y >= y0 - HALO + 1 && y < y1 + HALO - 1; };
+    auto row_ok_c = [&](int y) { return y >= y0 - HALO && y < y1 + HALO; };
+    // node index of the lane's even column in row y (y periodic); the odd column is the next one
+    auto node_of = [&](int y) {
+        return (uint32_t)D.off + (uint32_t)wrap(y, D.ny) * (uint32_t)D.nx + (uint32_t)xe[0];
+    };
+    // a clamped lane beyond an open end stands for the edge node in both columns
+    const bool clamp_pair = xe[1] != xe[0] + 1;
+
+    struct Pre {
+        PV f[9];
+        uint32_t m0, m1;   // class words of the two nodes
+        uint32_t fix;      // directions whose odd-column value is loaded on its own in stage A
+        AT wx0, wy0, wx1, wy1;
+    };
+    Pre pre;
+#pragma unroll
+    for (int a = 0; a < 9; a++) pre.f[a] = IO::zero();
+    pre.m0 = pre.m1 = SELF_SOLID;
+    pre.fix = 0;
+    pre.wx0 = pre.wy0 = pre.wx1 = pre.wy1 = AT(0);
+    uint32_t qm0 = 0, qm1 = 0;
+    struct Colour {
+        AT c0, c1, vx0, vx1, vy0, vy1;
+    };
+    Colour cset[2] = {{}, {}};
+    auto load_colour = [&](int yc, Colour &cs) {
+        const uint32_t vo = row_ok_c(yc) ? node_of(yc) * CB : NOWHERE;
+        const Pair<AT> c = load_f2(c_in, vo, 0), vx = load_f2(c_in, vo, CP), vy = load_f2(c_in, vo, 2 * CP);
+        cs.c0 = c.x;
+        cs.vx0 = vx.x;
+        cs.vy0 = vy.x;
+        cs.c1 = clamp_pair ? c.x : c.y;
+        cs.vx1 = clamp_pair ? vx.x : vx.y;
+        cs.vy1 = clamp_pair ? vy.x : vy.y;
+    };
+    auto load_mask = [&](int y) {
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r_mask, row_ok_a(y) ? node_of(y) * 2u : NOWHERE, 0, 0);
+        qm0 = v & 0xFFFFu;
+        qm1 = clamp_pair ? qm0 : v >> 16;
+    };
+    // fast-path column offsets of the pair pulled along e_x = +1, 0, -1
+    uint32_t colv[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) colv[k] = (gath[0] || gath[1]) ? (uint32_t)(xe[0] - 1 + k) * SB : NOWHERE;
+
+    auto prefetch = [&](int ya, Pre &p) {
+        const bool ok = row_ok_a(ya);
+        const uint32_t m0 = ok ? qm0 : SELF_SOLID, m1 = ok ? qm1 : SELF_SOLID;
+        const int yw = wrap(ya, D.ny);
+        const bool fast = ok && !A.own && !edge_item &&
+                          __builtin_amdgcn_ballot_w64(((m0 | m1) & (SELF_SOLID | 0xFFu)) != 0u) == 0;
+        uint32_t vo[9], so[9], vw, fix = 0;
+        if (fast) {
+            vw = NOWHERE;
+            const uint32_t row[3] = {
+                (uint32_t)D.off + (uint32_t)(yw == 0 ? D.ny - 1 : yw - 1) * (uint32_t)D.nx,
+                (uint32_t)D.off + (uint32_t)yw * (uint32_t)D.nx,
+                (uint32_t)D.off + (uint32_t)(yw == D.ny - 1 ? 0 : yw + 1) * (uint32_t)D.nx};
+#pragma unroll
+            for (int a = 0; a < 9; a++) {
+                vo[a] = colv[1 - EX[a]];
+                so[a] = (uint32_t)a * FP + row[1 - EY[a]] * SB;
+            }
+        } else {
+            const Nbr nb0 = make_nbr(D, xe[0], yw), nb1 = make_nbr(D, xe[1], yw);
+            const bool act0 = gath[0] && !(m0 & SELF_SOLID), act1 = gath[1] && !(m1 & SELF_SOLID);
+            const uint32_t self0 = (uint32_t)nb0.row[1] + (uint32_t)xe[0];
+            vw = (act0 && (m0 & FLUID_BND)) || (act1 && (m1 & FLUID_BND)) ? self0 * (2 * CB) : NOWHERE;
+#pragma unroll
+            for (int a = 0; a < 9; a++) {
+                const long long s0 = act0 ? pull_elem(nb0, xe[0], m0, a, A.own, A.plane) : -1;
+                const long long s1 = act1 ? pull_elem(nb1, xe[1], m1, a, A.own, A.plane) : -1;
+                long long e;
+                if (s0 < 0) {
+                    e = s1 < 0 ? -1 : s1 - 1;
+                } else {
+                    e = s0;
+                    if (s1 >= 0 && s1 != s0 + 1) fix |= 1u << a;
+                }
+                vo[a] = e < 0 ? NOWHERE : (uint32_t)e * SB;
+                so[a] = 0;
+            }
+        }
+        const Quad wn = load_f4(r_ns, vw);
+        p.wx0 = wn.a;
+        p.wy0 = wn.b;
+        p.wx1 = wn.c;
+        p.wy1 = wn.d;
+#pragma unroll
+        for (int a = 0; a < 9; a++) p.f[a] = IO::load(f_in, vo[a], so[a]);
+        p.m0 = m0;
+        p.m1 = m1;
+        p.fix = fix;
+        load_mask(ya + R);
+    };
+    auto put_colour = [&](int yc, const Colour &cs) {
+        const int sl = yc & (Q - 1);
+        s_c[sl][col[0]] = cs.c0;
+        s_c[sl][col[1]] = cs.c1;
+        s_vx[sl][col[0]] = cs.vx0;
+        s_vx[sl][col[1]] = cs.vx1;
+        s_vy[sl][col[0]] = cs.vy0;
+        s_vy[sl][col[1]] = cs.vy1;
+    };
+    auto replicate = [&](AT (*f)[TW], int sl) __attribute__((always_inline)) {
+        if (open_edge) {
+#pragma unroll
+            for (int k = 0; k < 2; k++)
+                if (edge_col[k] >= 0) f[sl][col[k]] = f[sl][edge_col[k]];
+        }
+    };
+
+    // populations of the two nodes (indices constant after unrolling, so they stay in registers)
+    AT d[2][9], dn[2][9];
+    AT rR[2] = {AT(0), AT(0)}, rB[2] = {AT(0), AT(0)}, rN[2] = {AT(0), AT(0)};
+    AT rRn[2] = {AT(0), AT(0)}, rBn[2] = {AT(0), AT(0)}, rNn[2] = {AT(0), AT(0)};
+#pragma unroll
+    for (int a = 0; a < 9; a++) d[0][a] = d[1][a] = dn[0][a] = dn[1][a] = AT(0);
+
+    // ---- A: gather, densities, colour indicator of row ya into LDS and dn / rRn / rBn / rNn
+    auto stage_a = [&](int ya, const Pre &p) __attribute__((always_inline)) {
+        const int sl = ya & (Q - 1);
+#pragma unroll
+        for (int a = 0; a < 9; a++) IO::decode(p.f[a], a, dn[0][a], dn[1][a]);
+        const int yw = wrap(ya, D.ny);
+        if (__builtin_amdgcn_ballot_w64(p.fix != 0u) != 0) {
+            // odd-column values whose source is not next to the even column's source
+            if (p.fix) {
+                const Nbr nb1 = make_nbr(D, xe[1], yw);
+#pragma unroll
+                for (int a = 0; a < 9; a++)
+                    if (p.fix & (1u << a)) {
+                        const long long e = pull_elem(nb1, xe[1], p.m1, a, A.own, A.plane);
+                        dn[1][a] = Codec<T>::load(A.fin + e, a);
+                    }
+            }
+        }
+        const uint32_t ms[2] = {p.m0, p.m1};
+        AT rn[2] = {AT(0), AT(0)};
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            if (gath[k] && !(ms[k] & SELF_SOLID)) {
+                const Nbr nb = make_nbr(D, xe[k], yw);
+                const int ck = col[k];
+                finish_gather<true>(A, D, xe[k], yw, ms[k], nb, !A.diag, dn[k], rRn[k], rBn[k],
+                                    [&](int a, AT &c, AT &vx, AT &vy) {
+                                        const int s2 = (ya - EY[a]) & (Q - 1);
+                                        const int l2 = ck - EX[a];
+                                        c = s_c[s2][l2];
+                                        vx = s_vx[s2][l2];
+                                        vy = s_vy[s2][l2];
+                                    });
+                rn[k] = colour_indicator(rRn[k], rBn[k]);
+                rNn[k] = rn[k];
+            }
+        }
+        s_m[sl][col[0]] = (uint16_t)p.m0;
+        s_m[sl][col[1]] = (uint16_t)p.m1;
+        s_rn[sl][col[0]] = rn[0];
+        s_rn[sl][col[1]] = rn[1];
+        s_wx[sl][col[0]] = p.wx0;
+        s_wy[sl][col[0]] = p.wy0;
+        s_wx[sl][col[1]] = p.wx1;
+        s_wy[sl][col[1]] = p.wy1;
+        replicate(s_rn, sl);
+        const bool wall = __builtin_amdgcn_ballot_w64(((p.m0 | p.m1) & SOLID_BND) != 0) != 0;
+        if (lane == 0) s_wall[sl] = wall;
+    };
+    auto any_wall = [&](int ya) __attribute__((always_inline)) {
+        int f = 0;
+#pragma unroll
+        for (int y = 0; y < R; y++) f |= s_wall[(ya + y) & (Q - 1)];
+        return __builtin_amdgcn_readfirstlane(f) != 0;
+    };
+
+    load_mask(r_first + R + w);
+    if (w < 2) {
+        load_colour(r_first + R - 1 + w, cset[0]);
+        put_colour(r_first + R - 1 + w, cset[0]);
+    }
+    load_colour(r_first + R + 1 + w, cset[0]);
+    prefetch(r_first + R + w, pre);
+    put_colour(r_first + R + 1 + w, cset[0]);
+    __syncthreads();
+    stage_a(r_first + R + w, pre);
+    load_colour(r_first + 2 * R + 1 + w, cset[1]);
+    {
+        // as many (dropped) stores as the loop issues between its colour loads and the prefetch
+#pragma unroll
+        for (int a = 0; a < 9; a++) IO::store(f_out, NOWHERE, (uint32_t)a * FP, IO::zero());
+        store_f2(c_out, NOWHERE, 0, AT(0), AT(0));
+        store_f2(c_out, NOWHERE, CP, AT(0), AT(0));
+        store_f2(c_out, NOWHERE, 2 * CP, AT(0), AT(0));
+    }
+    prefetch(r_first + 2 * R + w, pre);
+
+    auto iteration = [&](int r_, auto par_) __attribute__((always_inline)) {
+        constexpr int par = decltype(par_)::value;
+        const int r = __builtin_amdgcn_readfirstlane(r_);
+        load_colour(r + 3 * R + 1 + w, cset[par]);
+        __syncthreads();
+        const bool do_b = any_wall(r + R - 1), do_d = !scheme_b && any_wall(r + R - 3);
+        if (do_b) {
+            // ---- B: virtual colour indicator on outermost solid nodes (Eq. 29)
+            const int yb = r + R - 1 + w;
+            const int sl = yb & (Q - 1);
+            if (yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
+#pragma unroll
+                for (int k = 0; k < 2; k++) {
+                    const int ck = col[k];
+                    if (ck >= 2 && ck < TW - 2) {
+                        const uint32_t m = s_m[sl][ck];
+                        if ((m & SOLID_BND) && surface_energy) {
+                            s_rn[sl][ck] = P.cos_t;
+                        } else if (m & SOLID_BND) {
+                            AT num = AT(0), den = AT(0);
+#pragma unroll
+                            for (int a = 1; a < 9; a++) {
+                                if (m & (1u << (a - 1))) continue;
+                                const AT wa = wgt<AT>(a);
+                                num += wa * s_rn[(yb + EY[a]) & (Q - 1)][ck + EX[a]];
+                                den += wa;
+                            }
+                            s_rn[sl][ck] = num * rcp(den);
+                        }
+                    }
+                }
+            }
+            replicate(s_rn, sl);
+            __syncthreads();
+        }
+        // ---- C: colour gradient (Eq. 28), wetting correction, interface normal (Eq. 22)
+        {
+            const int yc = r + R - 2 + w;
+            const int sl = yc & (Q - 1);
+            if (yc >= y0 - HALO + 3 && yc < y1 + HALO - 3) {
+#pragma unroll
+                for (int k = 0; k < 2; k++) {
+                    const int ck = col[k];
+                    if (ck >= 3 && ck < TW - 3) {
+                        const uint32_t m = s_m[sl][ck];
+                        AT gx = AT(0), gy = AT(0), nx = AT(0), ny = AT(0);
+                        if (!(m & SELF_SOLID)) {
+                            AT sx = AT(0), sy = AT(0);
+#pragma unroll
+                            for (int a = 1; a < 9; a++) {
+                                const AT v = s_rn[(yc + EY[a]) & (Q - 1)][ck + EX[a]];
+                                if (EX[a]) sx = acc_nc(sx, wgt<AT>(a), v, EX[a]);
+                                if (EY[a]) sy = acc_nc(sy, wgt<AT>(a), v, EY[a]);
+                            }
+                            gx = AT(3) * sx;
+                            gy = AT(3) * sy;
+                            if (rec_cl && (m & FLUID_BND) && out[k] && yc >= y0 && yc < y1 &&
+                                fsqrt(gx * gx + gy * gy) > eps) {
+                                const int q = atomicAdd(A.cl_count, 1);
+                                if (q < A.cl_cap) A.cl_list[q] = yc * D.nx + X[k];
+                            }
+                            if ((m & FLUID_BND) && !surface_energy)
+                                wetting_correct(s_wx[sl][ck], s_wy[sl][ck], P.cos_t, P.sin_t, eps, gx, gy);
+                            const AT g = fsqrt(gx * gx + gy * gy);
+                            if (g > eps) unit_normal(gx, gy, g, nx, ny);
+                        }
+                        s_gx[sl][ck] = gx;
+                        s_gy[sl][ck] = gy;
+                        s_nx[sl][ck] = nx;
+                        s_ny[sl][ck] = ny;
+                    }
+                }
+            }
+            replicate(s_nx, sl);
+            replicate(s_ny, sl);
+        }
+        if (do_d) {
+            __syncthreads();
+            // ---- D: virtual interface normals on outermost solid nodes (Eq. 29, second BC)
+            const int yd = r + R - 3 + w;
+            const int sl = yd & (Q - 1);
+            if (yd >= y0 - 1 && yd < y1 + 1) {
+#pragma unroll
+                for (int k = 0; k < 2; k++) {
+                    const int ck = col[k];
+                    if (ck >= 4 && ck < TW - 4) {
+                        const uint32_t m = s_m[sl][ck];
+                        if (m & SOLID_BND) {
+                            AT numx = AT(0), numy = AT(0), den = AT(0);
+#pragma unroll
+                            for (int a = 1; a < 9; a++) {
+                                if (m & (1u << (a - 1))) continue;
+                                const AT wa = wgt<AT>(a);
+                                const int s2 = (yd + EY[a]) & (Q - 1);
+                                numx += wa * s_nx[s2][ck + EX[a]];
+                                numy += wa * s_ny[s2][ck + EX[a]];
+                                den += wa;
+                            }
+                            const AT iden = rcp(den);
+                            s_nx[sl][ck] = numx * iden;
+                            s_ny[sl][ck] = numy * iden;
+                        }
+                    }
+                }
+            }
+            replicate(s_nx, sl);
+            replicate(s_ny, sl);
+        }
+        put_colour(r + 2 * R + 1 + w, cset[1 - par]);
+        __syncthreads();
+        // ---- E: curvature (Eq. 13), force (Eq. 10), collision, recolouring state (Eq. 14)
+        {
+            const int ye = r + w;
+            const int sl = ye & (Q - 1);
+            const bool row_out = ye >= y0 && ye < y1;
+            AT o[2][9];
+            AT cst[2], bxs[2], bys[2];
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                const int ck = col[k];
+                // solid nodes store zero deviations and colour state (their initial values)
+                AT c = AT(0), bx = AT(0), by = AT(0), ux = AT(0), uy = AT(0);
+#pragma unroll
+                for (int a = 0; a < 9; a++) o[k][a] = AT(0);
+                const uint32_t me = s_m[sl][ck];
+                if (out[k] && row_out && !(me & SELF_SOLID)) {
+                    AT dxnx = AT(0), dynx = AT(0), dxny = AT(0), dyny = AT(0);
+                    if (scheme_b && (me & FLUID_BND)) {
+                        const AT nx0 = s_nx[sl][ck], ny0 = s_ny[sl][ck];
+                        AT den = AT(0);
+#pragma unroll
+                        for (int a = 1; a < 9; a++) {
+                            if (me & (1u << (a - 1))) continue;
+                            const int s2 = (ye + EY[a]) & (Q - 1);
+                            const AT vx = s_nx[s2][ck + EX[a]] - nx0, vy = s_ny[s2][ck + EX[a]] - ny0;
+                            if (EX[a]) {
+                                dxnx += wgt<AT>(a) * vx * AT(EX[a]);
+                                dxny += wgt<AT>(a) * vy * AT(EX[a]);
+                            }
+                            if (EY[a]) {
+                                dynx += wgt<AT>(a) * vx * AT(EY[a]);
+                                dyny += wgt<AT>(a) * vy * AT(EY[a]);
+                            }
+                            den += wgt<AT>(a);
+                        }
+                        const AT iden = rcp(den);
+                        dxnx *= iden;
+                        dynx *= iden;
+                        dxny *= iden;
+                        dyny *= iden;
+                    } else {
+#pragma unroll
+                        for (int a = 1; a < 9; a++) {
+                            const int s2 = (ye + EY[a]) & (Q - 1);
+                            const AT vx = s_nx[s2][ck + EX[a]], vy = s_ny[s2][ck + EX[a]];
+                            if (EX[a]) {
+                                dxnx += wgt<AT>(a) * vx * AT(EX[a]);
+                                dxny += wgt<AT>(a) * vy * AT(EX[a]);
+                            }
+                            if (EY[a]) {
+                                dynx += wgt<AT>(a) * vx * AT(EY[a]);
+                                dyny += wgt<AT>(a) * vy * AT(EY[a]);
+                            }
+                        }
+                        dxnx *= AT(3);
+                        dynx *= AT(3);
+                        dxny *= AT(3);
+                        dyny *= AT(3);
+                    }
+                    const AT nx = s_nx[sl][ck], ny = s_ny[sl][ck];
+                    const AT gx = s_gx[sl][ck], gy = s_gy[sl][ck];
+                    const AT kappa = -nx * nx * dyny - ny * ny * dxnx + nx * ny * (dynx + dxny);
+                    const AT Fx = P.half_sigma * kappa * gx;
+                    const AT Fy = P.half_sigma * kappa * gy;
+                    AT rho;
+                    collide(D, d[k], Fx, Fy, rN[k], o[k], rho, ux, uy);
+                    const AT rs = rR[k] + rB[k];
+                    c = quotient(rR[k], rs);
+                    const AT b = P.beta * rB[k] * c;
+                    bx = b * nx;
+                    by = b * ny;
+                    if (!isfinite(rho + ux + uy)) atomicOr(A.flag, 1);
+                }
+                if (A.diag) {
+                    c = ux;
+                    bx = uy;
+                }
+                cst[k] = c;
+                bxs[k] = bx;
+                bys[k] = by;
+            }
+            const uint32_t nd = node_of(ye);
+            const bool st = out[0] && row_out;
+            const uint32_t vf = st ? nd * SB : NOWHERE, vc = st ? nd * CB : NOWHERE;
+#pragma unroll
+            for (int a = 0; a < 9; a++) IO::store(f_out, vf, (uint32_t)a * FP, IO::encode(o[0][a], o[1][a], a));
+            store_f2(c_out, vc, 0, cst[0], cst[1]);
+            store_f2(c_out, vc, CP, bxs[0], bxs[1]);
+            store_f2(c_out, vc, 2 * CP, bys[0], bys[1]);
+        }
+#pragma unroll
+        for (int a = 0; a < 9; a++) {
+            d[0][a] = dn[0][a];
+            d[1][a] = dn[1][a];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            rR[k] = rRn[k];
+            rB[k] = rBn[k];
+            rN[k] = rNn[k];
+        }
+        stage_a(r + 2 * R + w, pre);
+        prefetch(r + 3 * R + w, pre);
+    };
+    for (int r = r_first;; r += 2 * R) {
+        iteration(r, std::integral_constant<int, 0>());
+        if (r + R >= y1) break;
+        iteration(r + R, std::integral_constant<int, 1>());
+        if (r + 2 * R >= y1) break;
+    }
+}
+
 // ------------------------------------------------------------- decode to FP64 fields
 template <class T>
 __global__ void read_kernel(const StepArgs<T, typename Codec<T>::AT> A, int dom, uint32_t which,
@@ -1234,7 +1816,9 @@ __global__ __launch_bounds__(DIAG_THREADS) void crossing_kernel(
     __syncthreads();
     if (y >= 0 && y < D.ny) {
         for (int x = threadIdx.x; x < D.nx - 1; x += DIAG_THREADS) {
-            if (x >= first) break;
+            // early exit once some thread has found a crossing further left (an atomic read:
+            // other threads lower the word concurrently; the result is read after the barrier)
+            if (x >= __hip_atomic_load(&first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
             if (rho_n_at(A, D, x, y) > 0.0 && rho_n_at(A, D, x + 1, y) <= 0.0) atomicMin(&first, x);
         }
     }
@@ -1251,8 +1835,18 @@ __global__ __launch_bounds__(DIAG_THREADS) void crossing_kernel(
 
 // ------------------------------------------------------------------- launchers
 template <class T, bool WV>
-static hipError_t step_t(const void *args, int n_items, int waves, int cols, hipStream_t s) {
+static hipError_t step_t(const void *args, int n_items, int waves, int cols, int npl, hipStream_t s) {
     const auto &A = *static_cast<const StepArgs<T, typename Codec<T>::AT> *>(args);
+    if constexpr (sizeof(typename Codec<T>::AT) == 4) {
+        if (npl == 2) {
+            if (waves == 8)
+                hipLaunchKernelGGL((pair_kernel<T, 8, WV>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
+            else
+                hipLaunchKernelGGL((pair_kernel<T, 4, WV>), dim3(n_items), dim3(TILE_LANES * 4), 0, s, A);
+            return hipGetLastError();
+        }
+    }
+    if (npl != 1) return hipErrorInvalidValue;
     if (cols == 2)
         hipLaunchKernelGGL((step_kernel<T, 4, 2, WV>), dim3(n_items), dim3(TILE_LANES * 8), 0, s, A);
     else if (waves == 8)
@@ -1263,20 +1857,20 @@ static hipError_t step_t(const void *args, int n_items, int waves, int cols, hip
 }
 
 template <class T>
-static hipError_t step_v(const void *args, int n_items, int waves, int cols, bool variants,
+static hipError_t step_v(const void *args, int n_items, int waves, int cols, int npl, bool variants,
                          hipStream_t s) {
-    return variants ? step_t<T, true>(args, n_items, waves, cols, s)
-                    : step_t<T, false>(args, n_items, waves, cols, s);
+    return variants ? step_t<T, true>(args, n_items, waves, cols, npl, s)
+                    : step_t<T, false>(args, n_items, waves, cols, npl, s);
 }
 
-hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols,
+hipError_t launch_step(int storage, const void *args, int n_items, int waves, int cols, int npl,
                        bool variants, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
     switch (storage) {
-        case 0: return step_v<double>(args, n_items, waves, cols, variants, s);
-        case 1: return step_v<float>(args, n_items, waves, cols, variants, s);
-        case 2: return step_v<__half>(args, n_items, waves, cols, variants, s);
-        case 3: return step_v<C16>(args, n_items, waves, cols, variants, s);
+        case 0: return step_v<double>(args, n_items, waves, cols, npl, variants, s);
+        case 1: return step_v<float>(args, n_items, waves, cols, npl, variants, s);
+        case 2: return step_v<__half>(args, n_items, waves, cols, npl, variants, s);
+        case 3: return step_v<C16>(args, n_items, waves, cols, npl, variants, s);
     }
     return hipErrorInvalidValue;
 }

@@ -54,7 +54,7 @@ PROTOTYPES = {
     "lbm_read_fields": (C.c_int, [C.c_void_p, C.c_int, C.c_uint32, C.c_void_p, C.c_size_t]),
     "lbm_mass": (C.c_int, [C.c_void_p, _dp]),
     "lbm_steps_taken": (C.c_int64, [C.c_void_p]),
-    "lbm_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int]),
+    "lbm_set_tile": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]),
     "lbm_get_tile": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "lbm_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
     "lbm_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_double)]),
@@ -181,15 +181,16 @@ class Lattice:
     def steps(self) -> int:
         return int(load_library().lbm_steps_taken(self._h))
 
-    def set_tile(self, chunk_rows: int = 0, waves: int = 0, cols: int = 0):
-        _check(load_library().lbm_set_tile(self._h, int(chunk_rows), int(waves), int(cols)))
+    def set_tile(self, chunk_rows: int = 0, waves: int = 0, cols: int = 0, cols_per_lane: int = 0):
+        _check(load_library().lbm_set_tile(self._h, int(chunk_rows), int(waves), int(cols),
+                                           int(cols_per_lane)))
 
     @property
     def tile(self) -> dict:
         """The step's tile shape in use and its work items (blocks per launch)."""
-        out = (C.c_int * 4)()
+        out = (C.c_int * 5)()
         _check(load_library().lbm_get_tile(self._h, out))
-        return dict(chunk_rows=out[0], waves=out[1], cols=out[2], items=out[3])
+        return dict(chunk_rows=out[0], waves=out[1], cols=out[2], items=out[3], cols_per_lane=out[4])
 
     def set_graph(self, launches: int):
         """Replay runs of `launches` steps (even; 0 = off) as one HIP graph launch each."""
@@ -201,10 +202,11 @@ class Lattice:
         temporary device buffer and restored, so the simulation is unchanged."""
         n = int(load_library().lbm_state_size(self._h))
         buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
-        out = (C.c_double * 4)()
+        out = (C.c_double * 5)()
         _check(load_library().lbm_autotune(self._h, int(steps), C.c_void_p(buf.data_ptr()), out))
         del buf
-        return dict(chunk_rows=int(out[0]), waves=int(out[1]), cols=int(out[2]), ms_per_step=out[3])
+        return dict(chunk_rows=int(out[0]), waves=int(out[1]), cols=int(out[2]), ms_per_step=out[3],
+                    cols_per_lane=int(out[4]))
 
     def synchronize(self):
         self.stream.synchronize()

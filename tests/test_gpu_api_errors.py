@@ -59,9 +59,9 @@ def test_bad_arguments_leave_the_state_untouched():
     assert L.lbm_read_fields(lat._h, 0, 1, dp, 10) == ENOMEM        # output too small
     assert L.lbm_read_fields(lat._h, 3, 1, dp, 10) == EINVAL        # no such domain
     assert L.lbm_read_fields(lat._h, 0, 64, dp, 10) == EINVAL       # unknown field bit
-    assert L.lbm_set_tile(lat._h, 6, 0, 0) == EINVAL                 # chunk not a multiple of 4
-    assert L.lbm_set_tile(lat._h, 0, 3, 0) == EINVAL                 # waves
-    assert L.lbm_set_tile(lat._h, 0, 8, 2) == EINVAL                 # 8 x 2 not provided
+    assert L.lbm_set_tile(lat._h, 6, 0, 0, 0) == EINVAL                 # chunk not a multiple of 4
+    assert L.lbm_set_tile(lat._h, 0, 3, 0, 0) == EINVAL                 # waves
+    assert L.lbm_set_tile(lat._h, 0, 8, 2, 0) == EINVAL                 # 8 x 2 not provided
     assert np.array_equal(lat.pops(0), before)
     ref = _lat().step(30).pops(0)
     assert np.array_equal(lat.step(30).pops(0), ref)

@@ -69,8 +69,8 @@ def test_fullsize_sweep_c16_sampled_channels():
     from paper_1707_00198_amd.lbm import Lattice
     setups = W.cfg_sweep()
     lat = Lattice(setups, storage="c16")
-    # the launch configuration bench.py times: 64-row chunks of 54-column strips, 4 wavefronts
-    assert lat.tile == dict(chunk_rows=64, waves=4, cols=1, items=31744)
+    # the built-in launch configuration: 64-row chunks of 54-column strips, 4 wavefronts
+    assert lat.tile == dict(chunk_rows=64, waves=4, cols=1, items=31744, cols_per_lane=1)
     lat.step(30)
     heights = {}
     for d, s in enumerate(setups):

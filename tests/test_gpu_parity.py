@@ -161,8 +161,9 @@ def test_chunking_does_not_change_results():
 
 @pytest.mark.parametrize("idx", range(6))
 def test_parity_fp64_two_wavefront_tiles(idx):
-    """The 128-column tiles (two wavefronts per row, the default of the 4-byte storages) on the
-    FP64 path against the oracle, including open channels whose edge columns are replicated."""
+    """The 128-column tiles (two wavefronts per row; not the built-in shape of any storage, but
+    one that lbm_set_tile and lbm_autotune can select) on the FP64 path against the oracle,
+    including open channels whose edge columns are replicated."""
     s = small_cases()[idx]
     lat = lattice([s])
     lat.set_tile(0, 4, 2)

@@ -2,7 +2,10 @@
 
 * FP64 parity with the oracle (max-abs 1e-10 per population) for scheme (b) (Eq. 48), the
   surface-energy rule and both together, on flat, staircase-cylinder (eighth-order normals),
-  analytic-cylinder and channel cases;
+  analytic-cylinder and channel cases; domains under the surface-energy rule are held to 1e-8,
+  because that rule amplifies rounding of the colour split (the oracle with unit-roundoff noise
+  in the colour split spreads by up to 2e-9 over 200 steps: tests/conditioning.py,
+  test_oracle_wetting_variants.test_surface_energy_rule_amplifies_colour_split_rounding);
 * domains with different variants in one launch match their own oracle runs;
 * Table II set-up (flat wall, M = 1 and 100, five angles) under schemes (a) and (b): every
   spurious velocity within a factor 1.35 of the printed one, and scheme (b) above scheme (a)
@@ -22,6 +25,11 @@ from paper_1707_00198_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
+TOL_SURFACE_ENERGY = 1e-8
+
+
+def _tol(s):
+    return TOL_SURFACE_ENERGY if s.wetting & W.WET_SURFACE_ENERGY else TOL
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
 VARIANTS = {"b": W.WET_SCHEME_B, "se": W.WET_SURFACE_ENERGY,
             "se+b": W.WET_SCHEME_B | W.WET_SURFACE_ENERGY}
@@ -59,9 +67,9 @@ def test_parity_fp64_variants(idx, variant):
     g = _lattice([s]).step(steps).pops(0)
     r = _oracle(s).step(steps).pops()
     err = np.abs(g - r).max()
-    print(f"  max |gpu - oracle| = {err:.3e}", flush=True)
+    print(f"  max |gpu - oracle| = {err:.3e} (bar {_tol(s):g})", flush=True)
     assert np.isfinite(g).all()
-    assert err <= TOL
+    assert err <= _tol(s)
 
 
 def test_parity_mixed_variants_in_one_launch():
@@ -74,8 +82,8 @@ def test_parity_mixed_variants_in_one_launch():
     lat = _lattice(setups).step(150)
     for d, s in enumerate(setups):
         err = np.abs(lat.pops(d) - _oracle(s).step(150).pops()).max()
-        print(f"{s.name}: {err:.3e}", flush=True)
-        assert err <= TOL
+        print(f"{s.name}: {err:.3e} (bar {_tol(s):g})", flush=True)
+        assert err <= _tol(s)
 
 
 def test_table2_spurious_velocity_schemes_a_and_b():
