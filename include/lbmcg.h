@@ -236,6 +236,19 @@ int lbm_diag_region_mass(lbm_ctx *ctx, int domain, const uint8_t *region_dev, do
 int lbm_diag_crossings(lbm_ctx *ctx, int domain, const int32_t *rows_host, int n_rows,
                        double *out_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): lbm_diag_crossings without a diagnostics buffer.  Same
+ * arguments and results, but the row list and the results are staged in a static device array of
+ * the library (one per GPU, LBM_NOALLOC_MAX_ROWS rows, 48 KiB, held until the process ends) and
+ * copied from / to the caller's plain host arrays; nothing is allocated, no diagnostics buffer is
+ * needed.  The array is looked up once per device by lbm_create (on the device current there).
+ * Synchronises the context's stream.  LBM_EINVAL for n_rows outside [1, LBM_NOALLOC_MAX_ROWS] or a
+ * row outside the domain, before any device work.  Every call on one GPU, from any context or
+ * thread, shares that GPU's array: calls that overlap in time on one GPU race. */
+#define LBM_NOALLOC_MAX_ROWS 4096
+int lbm_diag_crossings_noalloc(lbm_ctx *ctx, int domain, const int32_t *rows_host, int n_rows,
+                               double *out_host);
+
 /* The dynamic contact-line list (the part of the outermost fluid nodes where the wetting
  * condition of Sec. II C acts): the outermost fluid nodes of `domain` whose colour gradient of
  * the current state (Eq. 28 with the virtual values, before the correction of Eqs. 30-36) has

@@ -273,6 +273,9 @@ struct lbm_ctx {
     int graph_steps = 0;
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // device current at lbm_create, and its static staging array of lbm_diag_crossings_noalloc
+    int device = 0;
+    void *noalloc = nullptr;
 };
 
 namespace {
@@ -622,7 +625,14 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
                     L.state_bytes, L.scratch_bytes);
     if (((uintptr_t)state_dev | (uintptr_t)scratch_dev) & 255)
         return fail(LBM_EINVAL, "device buffers must be 256-byte aligned");
+    // the device's static staging array, looked up once per device with the device current
+    int device = 0;
+    void *noalloc = nullptr;
+    HIP_OK(hipGetDevice(&device));
+    HIP_OK(noalloc_scratch(device, &noalloc));
     lbm_ctx *c = new lbm_ctx();
+    c->device = device;
+    c->noalloc = noalloc;
     c->n = n;
     c->storage = storage;
     for (int i = 0; i < n; i++) c->variants = c->variants || domains[i].wetting != 0;
@@ -996,6 +1006,29 @@ int lbm_diag_crossings(lbm_ctx *c, int domain, const int32_t *rows_host, int n_r
     HIP_OK(hipMemcpyAsync(c->diag_host, out, (size_t)n_rows * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     std::memcpy(out_host, c->diag_host, (size_t)n_rows * sizeof(double));
+    return LBM_OK;
+}
+
+int lbm_diag_crossings_noalloc(lbm_ctx *c, int domain, const int32_t *rows_host, int n_rows,
+                               double *out_host) {
+    if (!c || !rows_host || !out_host) return fail(LBM_EINVAL, "null argument");
+    if (domain < 0 || domain >= c->n) return fail(LBM_EINVAL, "domain %d out of range", domain);
+    if (n_rows < 1 || n_rows > NOALLOC_ROWS)
+        return fail(LBM_EINVAL, "row count %d outside [1, %d] (size of the static staging array)", n_rows,
+                    NOALLOC_ROWS);
+    for (int k = 0; k < n_rows; k++)
+        if (rows_host[k] < 0 || rows_host[k] >= c->desc[domain].ny)
+            return fail(LBM_EINVAL, "row %d outside the domain", rows_host[k]);
+    if (!c->noalloc) return fail(LBM_ESTATE, "no static staging array for this context's device");
+    // rows in, crossing kernel, results out, all on the context's stream; the caller's host
+    // arrays are used directly (no pinned staging), and the stream is drained before returning
+    HIP_OK(hipMemcpyAsync(c->noalloc, rows_host, (size_t)n_rows * sizeof(int32_t), hipMemcpyHostToDevice,
+                          c->stream));
+    AnyArgs a = make_args(c, c->parity);
+    HIP_OK(launch_crossings_noalloc(c->storage, a.bytes, domain, c->noalloc, n_rows, c->stream));
+    HIP_OK(hipMemcpyAsync(out_host, static_cast<char *>(c->noalloc) + NOALLOC_OUT_OFFSET,
+                          (size_t)n_rows * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
     return LBM_OK;
 }
 

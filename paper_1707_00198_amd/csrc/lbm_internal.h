@@ -128,4 +128,16 @@ hipError_t launch_region_mass(int storage, const void *args, int dom, const uint
 hipError_t launch_crossings(int storage, const void *args, int dom, const int *rows, int n_rows,
                             double *out, hipStream_t s);
 
+// Staging of lbm_diag_crossings_noalloc in a static device array (lbm_kernels.hip): up to
+// NOALLOC_ROWS row indices, then as many FP64 results at byte NOALLOC_OUT_OFFSET.
+constexpr int NOALLOC_ROWS = 4096;
+constexpr size_t NOALLOC_OUT_OFFSET = NOALLOC_ROWS * sizeof(int);
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_OUT_OFFSET + NOALLOC_ROWS * sizeof(double);
+// Device address of that array on `device`, which must be the current device; looked up once
+// per device with hipGetSymbolAddress and cached.
+hipError_t noalloc_scratch(int device, void **out);
+// crossing_kernel with rows and results in the array at scratch_dev (noalloc_scratch's address).
+hipError_t launch_crossings_noalloc(int storage, const void *args, int dom, void *scratch_dev,
+                                    int n_rows, hipStream_t s);
+
 }  // namespace lbmcg

@@ -31,6 +31,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "lbm_internal.h"
 
 namespace lbmcg {
@@ -2016,6 +2018,42 @@ hipError_t launch_crossings(int storage, const void *args, int dom, const int *r
     }
 #undef CALL
     return hipErrorInvalidValue;
+}
+
+// ------------------------------------------ device-resident staging of the no-alloc crossings
+// Row list (NOALLOC_ROWS ints) followed by the results (NOALLOC_ROWS doubles) of
+// lbm_diag_crossings_noalloc.  One copy per GPU, kept until the process ends.  In host code the
+// name `scratch` is only a host-side stand-in for the symbol: kernels get the device address
+// that hipGetSymbolAddress returns for the current device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        // once per device, with that device current (the caller's responsibility)
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_crossings_noalloc(int storage, const void *args, int dom, void *scratch_dev,
+                                    int n_rows, hipStream_t s) {
+    const int *rows = static_cast<const int *>(scratch_dev);
+    double *out = reinterpret_cast<double *>(static_cast<char *>(scratch_dev) + NOALLOC_OUT_OFFSET);
+    return launch_crossings(storage, args, dom, rows, n_rows, out, s);
 }
 
 }  // namespace lbmcg

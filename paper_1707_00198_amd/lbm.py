@@ -66,6 +66,7 @@ PROTOTYPES = {
     "lbm_diag_velocity": (C.c_int, [C.c_void_p, C.c_int, _dp]),
     "lbm_diag_region_mass": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, _dp]),
     "lbm_diag_crossings": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int, _dp]),
+    "lbm_diag_crossings_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int, _dp]),
     "lbm_diag_contact_line": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.c_int,
                                         C.POINTER(C.c_int)]),
     "lbm_last_error": (C.c_char_p, []),
@@ -289,6 +290,15 @@ class Lattice:
         out = np.empty(len(rows))
         _check(load_library().lbm_diag_crossings(self._h, dom, _ptr(rows, C.c_int32), len(rows),
                                                  _ptr(out, C.c_double)))
+        return out
+
+    def crossings_noalloc(self, dom: int, rows) -> np.ndarray:
+        """As crossings(), through the entry point that allocates nothing (static device staging,
+        no diagnostics buffer)."""
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        out = np.empty(len(rows))
+        _check(load_library().lbm_diag_crossings_noalloc(self._h, dom, _ptr(rows, C.c_int32), len(rows),
+                                                         _ptr(out, C.c_double)))
         return out
 
     def contact_line(self, dom: int) -> np.ndarray:
