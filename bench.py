@@ -59,6 +59,9 @@ def parse(argv=None):
                     help="step launches per HIP graph replay (0: direct launches; default: graphs "
                          "for the sweep, as many launches as the timed steps allow up to 100)")
     ap.add_argument("--chunk-rows", type=int, default=0)
+    ap.add_argument("--shape", default=None,
+                    help="waves,cols,cols_per_lane of the timed lattice's tile (lbm_set_tile; implies "
+                         "--tile builtin for the chunk height unless --chunk-rows is given)")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--no-builtin-figure", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -120,7 +123,8 @@ def graph_launches(requested, steps, default_on):
     return n if n >= 2 else 0
 
 
-def time_lattice(setups, storage, steps, warmup, chunk_rows=0, tile="builtin", graph=0, lat=None):
+def time_lattice(setups, storage, steps, warmup, chunk_rows=0, tile="builtin", graph=0, lat=None,
+                 shape=None):
     """Build a lattice (or reuse `lat`), set its shape and graph mode, run `warmup` untimed steps,
     then time `steps` steps with HIP events on the lattice's stream."""
     import torch
@@ -133,8 +137,8 @@ def time_lattice(setups, storage, steps, warmup, chunk_rows=0, tile="builtin", g
         t = lat.autotune(steps=10)
         print(f"[bench] autotuned tile: {t}", flush=True)
     else:
-        lat.set_tile(chunk_rows)
-    rule = "autotuned" if tile == "autotune" else ("set" if chunk_rows else "built-in")
+        lat.set_tile(chunk_rows, *(shape or ()))
+    rule = "autotuned" if tile == "autotune" else ("set" if chunk_rows or shape else "built-in")
     shape = dict(lat.tile, rule=rule)
     lat.set_graph(graph)
     lat.step(warmup)
@@ -393,14 +397,16 @@ def main():
         if args.storage:
             storage = args.storage
         sweep = args.workload == "sweep"
-        tile = args.tile or ("autotune" if sweep else "builtin")
+        shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
+        tile = args.tile or ("autotune" if sweep and shape is None else "builtin")
         graph = graph_launches(args.graph, args.steps, sweep)
         print(f"[bench] workload {args.workload}: {len(setups)} domains, "
               f"{sum(s.fluid_nodes for s in setups)} fluid nodes, storage {storage}, tile {tile}, "
               f"graph launches {graph}", flush=True)
         from paper_1707_00198_amd.lbm import Lattice
         lat = Lattice(setups, storage=storage)
-        head = time_lattice(setups, storage, args.steps, args.warmup, args.chunk_rows, tile, graph, lat=lat)
+        head = time_lattice(setups, storage, args.steps, args.warmup, args.chunk_rows, tile, graph, lat=lat,
+                            shape=shape)
         print(f"[bench] {args.workload} {storage}: {head['mlups']:.1f} MLUPS, "
               f"{head['ms_per_step']:.4f} ms/step ({head['tile']}, graph launches {graph})", flush=True)
         if not args.no_builtin_figure and (tile != "builtin" or graph):

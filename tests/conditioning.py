@@ -34,16 +34,33 @@ def colour_split_noise(pops: np.ndarray, rng, rel: float) -> np.ndarray:
     return out
 
 
+def fraction_rounded_to_fp32(pops: np.ndarray) -> np.ndarray:
+    """(2, 9, ny, nx) populations whose red fraction f_R / (f_R + f_B) is rounded to FP32 in every
+    population that holds both colours (totals kept): colour tails below the FP32 resolution of the
+    total vanish, as they do in FP32 arithmetic."""
+    r, b = pops[0], pops[1]
+    tot = r + b
+    both = (r > 0) & (b > 0)
+    frac = np.where(both, (r / np.where(both, tot, 1.0)).astype(np.float32).astype(np.float64), 0.0)
+    out = pops.copy()
+    out[0] = np.where(both, frac * tot, r)
+    out[1] = np.where(both, tot - out[0], b)
+    return out
+
+
 def one_step_sensitivity(make_oracle, pops: np.ndarray, rel: float, seeds=(11, 12, 13)):
     """One oracle step from `pops`, and the largest change of each output population when the
-    input's colour split is perturbed at level `rel` (several seeds).  Returns (ref, spread)."""
+    input's colour split is perturbed: at level `rel` (several seeds), and by rounding each red
+    fraction to FP32.  Returns (ref, spread)."""
     o = make_oracle()
     o.set_pops(pops)
     ref = o.step(1).pops()
     spread = np.zeros_like(ref)
-    for seed in seeds:
+    variants = [colour_split_noise(pops, np.random.default_rng(seed), rel) for seed in seeds]
+    variants.append(fraction_rounded_to_fp32(pops))
+    for v in variants:
         o = make_oracle()
-        o.set_pops(colour_split_noise(pops, np.random.default_rng(seed), rel))
+        o.set_pops(v)
         spread = np.maximum(spread, np.abs(o.step(1).pops() - ref))
     return ref, spread
 

@@ -27,13 +27,15 @@ on the direction of n one row in, where |grad rho^N| is a rounding-sized tail (r
 n = 0 only below eps).  The oracle itself, with unit-roundoff noise in the colour split after
 every step, spreads by up to 2e-9 over 200 steps there (against 3e-15 for the other models).
 So FP64 domains with that rule are held to 1e-8 instead of 1e-10.  In the one-step tests the
-oracle's own step is repeated from the same state with colour-split noise of 2^-18 of the total
-(a few units of the rounding of an FP32 sum of nine terms); a population whose result then moves
-by more than four times its tolerance is decided by rounding, not by the method.  Such
-populations exist only under the surface-energy rule (about 1 % of them, on the rows next to
-walls; in every other domain the noise moves no population by more than three times its
-tolerance, checked), and there they are held only to the size of the force term they carry (0.05); every
-other population is held to the tolerance.
+oracle's own step is repeated from the same state with the colour split perturbed the way FP32
+arithmetic perturbs it (noise of 2^-18 of the total, three seeds, and every red fraction rounded
+to FP32), and the largest change of each output population is its conditioning allowance.  In
+every domain without the surface-energy rule that allowance stays below three times the rounding
+tolerance (checked), and the populations are held to the rounding tolerance alone.  Under the
+rule, the ill-conditioned part is the wall band (fluid nodes within two nodes of a solid one: the
+first fluid row carries the O(1) wall gradient, its curvature reads the next row, streaming moves
+the result one node): there populations are held to 0.05, the size of the force term; everywhere
+else to the rounding tolerance plus four times the allowance.
 """
 import numpy as np
 import pytest
@@ -84,6 +86,16 @@ def _oracle(s):
     return oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **s.oracle_kwargs())
 
 
+def _wall_band(solid):
+    """Fluid nodes within two nodes (Chebyshev distance, periodic) of a solid node."""
+    near = np.zeros(solid.shape, dtype=bool)
+    sb = solid.astype(bool)
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            near |= np.roll(np.roll(sb, dy, axis=0), dx, axis=1)
+    return near & ~sb
+
+
 @pytest.mark.parametrize("variants", [False, True], ids=["plain", "variants"])
 @pytest.mark.parametrize("waves,cols", SHAPES, ids=[f"{w}x{c}" for w, c in SHAPES])
 def test_fp64_build_against_oracle(waves, cols, variants):
@@ -119,16 +131,22 @@ def test_fp32_arithmetic_build_one_step_from_gpu_state(storage, waves, cols, npl
         dev = np.abs(ref.sum(axis=0) - WEIGHTS[:, None, None] * s.params["rho0"] * fluid)
         base = np.broadcast_to((dev * rel + 2e-6)[None], ref.shape)
         err = np.abs(got - ref)
-        ill = spread > 4.0 * base
-        worst = (err / base)[~ill].max()
-        print(f"  {s.name} wetting={s.wetting}: max error / tolerance = {worst:.3f} over the "
-              f"well-conditioned populations; {100 * ill.mean():.2f} % decided by rounding "
-              f"(largest error there {err[ill].max() if ill.any() else 0.0:.2e})", flush=True)
+        se = bool(s.wetting & W.WET_SURFACE_ENERGY)
+        tol = base + 4.0 * spread if se else base
+        if se:
+            tol = np.where(_wall_band(s.solid)[None, None], 0.05, tol)
+        ratio = err / tol
+        worst = ratio.max()
+        k = np.unravel_index(np.argmax(ratio), ratio.shape)
+        widened = float((tol > 2.0 * base).mean()) if se else 0.0
+        print(f"  {s.name} wetting={s.wetting}: max error / tolerance = {worst:.3f} at (colour, "
+              f"alpha, y, x) = {k} (error {err[k]:.2e}, allowance {spread[k]:.2e}); bar widened at "
+              f"{100 * widened:.2f} % of the populations, largest error {err.max():.2e}", flush=True)
         assert np.isfinite(got).all() and worst <= 1.0
-        if s.wetting & W.WET_SURFACE_ENERGY:
-            assert ill.mean() < 0.02 and (not ill.any() or err[ill].max() < 0.05)
+        if se:
+            assert err.max() < 0.05
         else:
-            assert not ill.any() and (spread <= 3.0 * base).all()
+            assert (spread <= 3.0 * base).all()
 
 
 @pytest.mark.parametrize("storage", ["f32", "c16"])
