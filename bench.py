@@ -141,7 +141,8 @@ def time_lattice(setups, storage, steps, warmup, chunk_rows=0, tile="builtin", g
     rule = "autotuned" if tile == "autotune" else ("set" if chunk_rows or shape else "built-in")
     shape = dict(lat.tile, rule=rule)
     lat.set_graph(graph)
-    lat.step(warmup)
+    # the warm-up includes at least one replay of every graph the timed steps use
+    lat.step(max(warmup, 2 * graph + 1) if graph else warmup)
     torch.cuda.synchronize()
     stream = lat.stream
     e0 = torch.cuda.Event(enable_timing=True)

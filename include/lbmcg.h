@@ -139,8 +139,9 @@ int lbm_step(lbm_ctx *ctx, int64_t n_steps);
  * the context's stream, one graph launch per `launches` steps.  The initial state of a context
  * (node-local, not yet streamed; also after lbm_load_state of such a state) first takes one
  * direct step, and a remainder shorter than a graph is launched step by step.  The graphs are
- * rebuilt after lbm_set_tile and lbm_autotune.  Synchronises the stream.  LBM_EINVAL for an
- * odd or out-of-range count. */
+ * rebuilt after lbm_set_tile and lbm_autotune.  Both graphs are captured, instantiated and
+ * uploaded to the device by this call (rebuilt ones at their first replay).  Synchronises the
+ * stream.  LBM_EINVAL for an odd or out-of-range count; LBM_EDEVICE if a capture fails. */
 int lbm_set_graph(lbm_ctx *ctx, int launches);
 
 /* Autotuner of the step's tile shape on this context's own batch: times every provided shape,

@@ -151,6 +151,19 @@ struct Codec<C16> {
         const uint32_t r = min((mag + 0x7FFu + ((mag >> 12) & 1u)) >> 12, 0x7FFFu);
         return C16{(uint16_t)(r | ((b >> 16) & 0x8000u))};
     }
+    // The same code in fewer instructions, in the lower 16 bits of a 32-bit word (the upper
+    // bits are left undefined): the scaled value is clamped to the largest finite code while
+    // still an FP32 number (0x07FFF000 as bits), so the rounding carry cannot reach the unused
+    // exponent bits, and the round-to-nearest-even increment is added to the signed word
+    // directly (sign-magnitude: the magnitude rounds, the sign stays).  Equal to encode() for
+    // every finite input.
+    __device__ static uint32_t encode_lo(float v, int a) {
+        constexpr float top = 0x1.fffp-112f;  // bits 0x07FFF000
+        const float x = __builtin_amdgcn_fmed3f(v * enc(a), -top, top);
+        const uint32_t b = __float_as_uint(x);
+        const uint32_t t = b + 0x7FFu + ((b >> 12) & 1u);
+        return (t >> 12) | ((t >> 16) & 0x8000u);
+    }
 };
 
 // Periodic wrap of an index that is usually already in [0, n): one compare on the fast path.
@@ -512,6 +525,10 @@ struct Buf<C16> {
     __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, C16 v) {
         __builtin_amdgcn_raw_buffer_store_b16(v.bits, r, vo, so, 0);
     }
+    // store the lower half of a word (the form Codec<C16>::encode_lo returns)
+    __device__ static void store_lo(Rsrc r, uint32_t vo, uint32_t so, uint32_t w) {
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)w, r, vo, so, 0);
+    }
 };
 template <>
 struct Buf<uint16_t> {
@@ -695,7 +712,12 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     // one row of outputs: populations, then the colour state (c, vx, vy)
     auto store_row = [&](uint32_t vf, uint32_t vc, const AT (&o)[9], AT c, AT bx, AT by) {
 #pragma unroll
-        for (int a = 0; a < 9; a++) Buf<T>::store(f_out, vf, (uint32_t)a * FP, Codec<T>::encode(o[a], a));
+        for (int a = 0; a < 9; a++) {
+            if constexpr (std::is_same_v<T, C16>)
+                Buf<C16>::store_lo(f_out, vf, (uint32_t)a * FP, Codec<C16>::encode_lo(o[a], a));
+            else
+                Buf<T>::store(f_out, vf, (uint32_t)a * FP, Codec<T>::encode(o[a], a));
+        }
         Buf<AT>::store(c_out, vc, 0, c);
         Buf<AT>::store(c_out, vc, CP, bx);
         Buf<AT>::store(c_out, vc, 2 * CP, by);
