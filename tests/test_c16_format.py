@@ -63,6 +63,35 @@ def device_encode(v, scale_exp):
     return (r | ((t >> 16) & 0x8000)).astype(np.uint16)
 
 
+def device_encode_lo(v, scale_exp):
+    """numpy model of the step kernel's store-path encode: the scaled FP32 value clamped to
+    +-0x07FFF000 (as bits) by a median of three, the round-to-nearest-even increment added to the
+    signed word, and the sign moved to bit 15; only the lower 16 bits are stored."""
+    x = np.asarray(v, dtype=np.float32) * np.float32(2.0 ** (scale_exp - 120))
+    top = np.uint32(0x07FFF000).view(np.float32)
+    x = np.clip(x, -top, top)
+    b = x.view(np.uint32)
+    t = b + np.uint32(0x7FF) + ((b >> 12) & np.uint32(1))
+    return ((t >> 12) | ((t >> 16) & np.uint32(0x8000))).astype(np.uint16)
+
+
+@pytest.mark.parametrize("scale_exp", [9, 11, 13])
+def test_store_path_encode_equals_reference_encode(scale_exp):
+    """The shorter encode of the store path gives the reference encode's code for every finite
+    input: both signs, zero, subnormal and normal scaled values, exact ties, the largest codes
+    and saturation, and every FP32 word near the clamp boundary."""
+    rng = np.random.default_rng(2024)
+    S = 2.0 ** scale_exp
+    mags = 10.0 ** rng.uniform(-12, 1.0, 200000) / S * 2.0 ** 8
+    ties = [(exact_value(c) + exact_value(c + 1)) / 2 / Fraction(2) ** scale_exp
+            for c in (0, 1, 5, 6, 2047, 2048, 4095, 12345, 0x7FFD, 0x7FFE)]
+    edge = (np.arange(0x07FF0000, 0x08010000, 7, dtype=np.uint32).view(np.float32)
+            * np.float32(2.0 ** (120 - scale_exp)))
+    vals = np.concatenate([mags, [float(t) for t in ties], [0.0, 1e-38, 1e30], edge]).astype(np.float32)
+    vals = np.concatenate([vals, -vals])
+    assert np.array_equal(device_encode_lo(vals, scale_exp), device_encode(vals, scale_exp))
+
+
 @pytest.mark.parametrize("scale_exp", [9, 11, 13])
 def test_decode_matches_definition_for_every_code(scale_exp):
     codes = np.arange(0x10000, dtype=np.uint32)
