@@ -164,21 +164,31 @@ def time_lattice(setups, storage, steps, warmup, chunk_rows=0, tile="builtin", g
     return out
 
 
-def roofline_of(storage, fluid, ms_per_step, workload=None, traffic_path=None):
+def roofline_of(storage, fluid, ms_per_step, workload=None, traffic_path=None, tile=None):
+    """Roofline record of the step launch: algorithmic bytes over the event-timed launch, and the
+    counter-measured HBM bytes when a profile of this kernel source, workload, storage and tile
+    shape exists.  `tile` is the lattice's tile dict (the two-column kernel when
+    cols_per_lane = 2)."""
     bpl = BYTES_PER_LUP[storage]
     achieved = bpl * fluid / (ms_per_step * 1e-3) / 1e9
     traffic = None
     if workload is not None:
         traffic = measured_traffic(traffic_path or os.path.join(
-            ROOT, "profiles", f"step_kernel_{workload}_{storage}_hbm_bytes.md"), workload, storage)
+            ROOT, "profiles", f"step_kernel_{workload}_{storage}_hbm_bytes.md"), workload, storage, tile)
+    pair = bool(tile) and tile.get("cols_per_lane", 1) == 2
+    kernel = f"pair_kernel<{KERNEL[storage]}>" if pair else f"step_kernel<{KERNEL[storage]}>"
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel=f"step_kernel<{KERNEL[storage]}>", bytes_per_lup=bpl, lups_per_launch=fluid)
+                kernel=kernel, bytes_per_lup=bpl, lups_per_launch=fluid)
 
 
-def measured_traffic(path, workload, storage):
+TILE_KEYS = ("chunk_rows", "waves", "cols", "cols_per_lane")
+
+
+def measured_traffic(path, workload, storage, tile=None):
     """HBM bytes per launch from a committed counter summary (FETCH_SIZE + WRITE_SIZE, scaled by
-    a copy kernel), or None if there is none or the kernel source has changed since."""
+    a copy kernel), or None if there is none, the kernel source has changed since, or the summary
+    names a tile shape other than `tile` (when both are given)."""
     import hashlib
     import re
     if not os.path.exists(path):
@@ -190,6 +200,9 @@ def measured_traffic(path, workload, storage):
     src = os.path.join(ROOT, "paper_1707_00198_amd", "csrc", "lbm_kernels.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if t.get("kernel_source_sha256") != h or t.get("workload") != workload or t.get("storage") != storage:
+        return None
+    if tile and t.get("tile") and any(t["tile"].get(k) != tile.get(k, 1 if k == "cols_per_lane" else None)
+                                      for k in TILE_KEYS):
         return None
     return t.get("bytes_per_launch")
 
@@ -303,7 +316,7 @@ def run_wetting_batch(args, storage16):
     for st, doms in parts.items():
         r = time_lattice(doms, st, args.steps, args.warmup, args.chunk_rows,
                          args.tile or "builtin", graph_launches(args.graph, args.steps, False))
-        r["roofline"] = roofline_of(st, r["fluid"], r["ms_per_step"])
+        r["roofline"] = roofline_of(st, r["fluid"], r["ms_per_step"], tile=r["tile"])
         res[st] = r
         print(f"[bench] wetting_batch {st} context: {len(doms)} domains, {r['fluid']} fluid nodes, "
               f"{r['mlups']:.1f} MLUPS, {r['ms_per_step']:.4f} ms/step", flush=True)
@@ -421,7 +434,8 @@ def main():
         torch.cuda.empty_cache()
         n_doms = len(setups)
         dtype = ARITH[storage]
-        roofline = roofline_of(storage, head["fluid"], head["ms_per_step"], args.workload, args.traffic)
+        roofline = roofline_of(storage, head["fluid"], head["ms_per_step"], args.workload, args.traffic,
+                               head["tile"])
         storage_desc = storage
         del setups
 

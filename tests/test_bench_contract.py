@@ -47,3 +47,24 @@ def test_traffic_is_read_only_for_the_profiled_kernel_source(tmp_path):
     assert bench.measured_traffic(summary(h, storage="f64"), "sweep", "c16") is None
     assert bench.measured_traffic(str(tmp_path / "missing.md"), "sweep", "c16") is None
 
+
+def test_traffic_is_read_only_for_the_profiled_tile_shape(tmp_path):
+    """A summary measured on one tile shape is not reported for a run on another (the autotuner
+    may pick a different chunk height or the two-column kernel); the kernel name follows the
+    shape."""
+    src = os.path.join(ROOT, "paper_1707_00198_amd", "csrc", "lbm_kernels.hip")
+    import hashlib
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    shape = {"chunk_rows": 64, "waves": 4, "cols": 1, "cols_per_lane": 1}
+    p = tmp_path / "t.md"
+    p.write_text("```json\n" + json.dumps({"workload": "sweep", "storage": "c16", "kernel_source_sha256": h,
+                                            "bytes_per_launch": 7, "tile": shape}) + "\n```\n")
+    assert bench.measured_traffic(str(p), "sweep", "c16", dict(shape, items=31744, rule="autotuned")) == 7
+    assert bench.measured_traffic(str(p), "sweep", "c16", dict(shape, chunk_rows=48)) is None
+    assert bench.measured_traffic(str(p), "sweep", "c16", dict(shape, cols_per_lane=2)) is None
+    assert bench.measured_traffic(str(p), "sweep", "c16") == 7
+    r = bench.roofline_of("c16", 1000, 1.0, "sweep", str(p), dict(shape, cols_per_lane=2))
+    assert r["traffic"] is None and r["kernel"] == "pair_kernel<lbmcg::C16>"
+    r = bench.roofline_of("c16", 1000, 1.0, "sweep", str(p), shape)
+    assert r["traffic"] == 7 and r["kernel"] == "step_kernel<lbmcg::C16>"
+
