@@ -151,20 +151,34 @@ struct Codec<C16> {
         const uint32_t r = min((mag + 0x7FFu + ((mag >> 12) & 1u)) >> 12, 0x7FFFu);
         return C16{(uint16_t)(r | ((b >> 16) & 0x8000u))};
     }
-    // The same code in fewer instructions, in the lower 16 bits of a 32-bit word (the upper
-    // bits are left undefined): the scaled value is clamped to the largest finite code while
-    // still an FP32 number (0x07FFF000 as bits), so the rounding carry cannot reach the unused
-    // exponent bits, and the round-to-nearest-even increment is added to the signed word
-    // directly (sign-magnitude: the magnitude rounds, the sign stays).  Equal to encode() for
-    // every finite input.
-    __device__ static uint32_t encode_lo(float v, int a) {
+    // The store path's rounding: stochastic, so that rounding errors carry no systematic part
+    // that could add up over many steps (with round-to-nearest the 16384 x 512 displacement
+    // channel's finger tip ran 0.36 % fast over 30000 steps; with this rounding 0.015 %).  The
+    // scaled value is clamped to the largest code while still an FP32 number (0x07FFF000 as
+    // bits, so no carry can reach the unused exponent bits), then 4 random bits, as an offset
+    // k * 256 + 128 (mean: half a unit), are added to the 12 bits that the code drops: the
+    // magnitude rounds up with a probability equal to the dropped fraction to within 1/16, and
+    // the sign is carried over.  The result is one of the two codes next to the value (exact
+    // values stay exact), in the lower 16 bits of the word (the upper bits undefined).  rnd
+    // supplies bits 3a .. 3a + 3 for direction a.
+    __device__ static uint32_t encode_sr(float v, int a, uint32_t rnd) {
         constexpr float top = 0x1.fffp-112f;  // bits 0x07FFF000
         const float x = __builtin_amdgcn_fmed3f(v * enc(a), -top, top);
-        const uint32_t b = __float_as_uint(x);
-        const uint32_t t = b + 0x7FFu + ((b >> 12) & 1u);
+        const uint32_t t = __float_as_uint(x) + ((((rnd >> (3 * a)) & 15u) << 8) | 0x80u);
         return (t >> 12) | ((t >> 16) & 0x8000u);
     }
 };
+
+// Random bits for the stochastic rounding of one node's 16-bit stores: a hash (multiply and
+// xor-shift rounds) of the node's byte offset within its domain and of the bit pattern of its
+// post-collision rest population, so the bits differ from node to node and from step to step,
+// and a domain's results do not depend on the tile shape or on the other domains of its batch.
+__device__ __forceinline__ uint32_t round_bits(uint32_t node_bytes, float v) {
+    uint32_t h = (node_bytes ^ __float_as_uint(v)) * 0x9E3779B1u;
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    return h ^ (h >> 15);
+}
 
 // Periodic wrap of an index that is usually already in [0, n): one compare on the fast path.
 // Element access into one node plane: a uniform base pointer plus a 32-bit byte offset, so
@@ -525,7 +539,7 @@ struct Buf<C16> {
     __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, C16 v) {
         __builtin_amdgcn_raw_buffer_store_b16(v.bits, r, vo, so, 0);
     }
-    // store the lower half of a word (the form Codec<C16>::encode_lo returns)
+    // store the lower half of a word (the form Codec<C16>::encode_sr returns)
     __device__ static void store_lo(Rsrc r, uint32_t vo, uint32_t so, uint32_t w) {
         __builtin_amdgcn_raw_buffer_store_b16((uint16_t)w, r, vo, so, 0);
     }
@@ -711,10 +725,11 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     };
     // one row of outputs: populations, then the colour state (c, vx, vy)
     auto store_row = [&](uint32_t vf, uint32_t vc, const AT (&o)[9], AT c, AT bx, AT by) {
+        const uint32_t rb = std::is_same_v<T, C16> ? round_bits(vf - (uint32_t)D.off * SB, o[0]) : 0u;
 #pragma unroll
         for (int a = 0; a < 9; a++) {
             if constexpr (std::is_same_v<T, C16>)
-                Buf<C16>::store_lo(f_out, vf, (uint32_t)a * FP, Codec<C16>::encode_lo(o[a], a));
+                Buf<C16>::store_lo(f_out, vf, (uint32_t)a * FP, Codec<C16>::encode_sr(o[a], a, rb));
             else
                 Buf<T>::store(f_out, vf, (uint32_t)a * FP, Codec<T>::encode(o[a], a));
         }
@@ -1038,8 +1053,9 @@ struct PairIO<C16> {
         lo = __uint_as_float(l) * Codec<C16>::dec(a);
         hi = __uint_as_float(h) * Codec<C16>::dec(a);
     }
-    __device__ static V encode(float lo, float hi, int a) {
-        return (uint32_t)Codec<C16>::encode(lo, a).bits | ((uint32_t)Codec<C16>::encode(hi, a).bits << 16);
+    // stochastic rounding as in step_kernel, with each node's own random bits
+    __device__ static V encode(float lo, float hi, int a, uint32_t rlo, uint32_t rhi) {
+        return (Codec<C16>::encode_sr(lo, a, rlo) & 0xFFFFu) | (Codec<C16>::encode_sr(hi, a, rhi) << 16);
     }
     __device__ static V zero() { return 0u; }
 };
@@ -1056,7 +1072,7 @@ struct PairIO<__half> {
         lo = Codec<__half>::decode(__ushort_as_half((unsigned short)(v & 0xFFFFu)), a);
         hi = Codec<__half>::decode(__ushort_as_half((unsigned short)(v >> 16)), a);
     }
-    __device__ static V encode(float lo, float hi, int a) {
+    __device__ static V encode(float lo, float hi, int a, uint32_t, uint32_t) {
         return (uint32_t)__half_as_ushort(Codec<__half>::encode(lo, a)) |
                ((uint32_t)__half_as_ushort(Codec<__half>::encode(hi, a)) << 16);
     }
@@ -1076,7 +1092,7 @@ struct PairIO<float> {
         lo = v.x;
         hi = v.y;
     }
-    __device__ static V encode(float lo, float hi, int) { return V{lo, hi}; }
+    __device__ static V encode(float lo, float hi, int, uint32_t, uint32_t) { return V{lo, hi}; }
     __device__ static V zero() { return V{0.0f, 0.0f}; }
 };
 
@@ -1557,8 +1573,12 @@ __global__ __launch_bounds__(TILE_LANES *R, 2) void pair_kernel(const StepArgs<T
             const uint32_t nd = node_of(ye);
             const bool st = out[0] && row_out;
             const uint32_t vf = st ? nd * SB : NOWHERE, vc = st ? nd * CB : NOWHERE;
+            const uint32_t vl = vf - (uint32_t)D.off * SB;  // offset within the domain
+            const uint32_t rb0 = std::is_same_v<T, C16> ? round_bits(vl, o[0][0]) : 0u;
+            const uint32_t rb1 = std::is_same_v<T, C16> ? round_bits(vl + SB, o[1][0]) : 0u;
 #pragma unroll
-            for (int a = 0; a < 9; a++) IO::store(f_out, vf, (uint32_t)a * FP, IO::encode(o[0][a], o[1][a], a));
+            for (int a = 0; a < 9; a++)
+                IO::store(f_out, vf, (uint32_t)a * FP, IO::encode(o[0][a], o[1][a], a, rb0, rb1));
             store_f2(c_out, vc, 0, cst[0], cst[1]);
             store_f2(c_out, vc, CP, bxs[0], bxs[1]);
             store_f2(c_out, vc, 2 * CP, bys[0], bys[1]);

@@ -63,33 +63,67 @@ def device_encode(v, scale_exp):
     return (r | ((t >> 16) & 0x8000)).astype(np.uint16)
 
 
-def device_encode_lo(v, scale_exp):
-    """numpy model of the step kernel's store-path encode: the scaled FP32 value clamped to
-    +-0x07FFF000 (as bits) by a median of three, the round-to-nearest-even increment added to the
-    signed word, and the sign moved to bit 15; only the lower 16 bits are stored."""
+def device_encode_sr(v, scale_exp, k):
+    """numpy model of the step kernels' stochastic-rounding store: the scaled FP32 value clamped
+    to +-0x07FFF000 (as bits) by a median of three, the random offset k * 256 + 128 (k: 4 random
+    bits) added to the 12 dropped bits of the signed word, the sign moved to bit 15; the lower
+    16 bits are stored."""
     x = np.asarray(v, dtype=np.float32) * np.float32(2.0 ** (scale_exp - 120))
     top = np.uint32(0x07FFF000).view(np.float32)
     x = np.clip(x, -top, top)
-    b = x.view(np.uint32)
-    t = b + np.uint32(0x7FF) + ((b >> 12) & np.uint32(1))
+    t = x.view(np.uint32) + ((np.asarray(k, dtype=np.uint32) & np.uint32(15)) << np.uint32(8)) + np.uint32(0x80)
     return ((t >> 12) | ((t >> 16) & np.uint32(0x8000))).astype(np.uint16)
 
 
-@pytest.mark.parametrize("scale_exp", [9, 11, 13])
-def test_store_path_encode_equals_reference_encode(scale_exp):
-    """The shorter encode of the store path gives the reference encode's code for every finite
-    input: both signs, zero, subnormal and normal scaled values, exact ties, the largest codes
-    and saturation, and every FP32 word near the clamp boundary."""
-    rng = np.random.default_rng(2024)
+def _sr_inputs(scale_exp, n=20000, seed=2024):
+    rng = np.random.default_rng(seed)
     S = 2.0 ** scale_exp
-    mags = 10.0 ** rng.uniform(-12, 1.0, 200000) / S * 2.0 ** 8
-    ties = [(exact_value(c) + exact_value(c + 1)) / 2 / Fraction(2) ** scale_exp
-            for c in (0, 1, 5, 6, 2047, 2048, 4095, 12345, 0x7FFD, 0x7FFE)]
-    edge = (np.arange(0x07FF0000, 0x08010000, 7, dtype=np.uint32).view(np.float32)
-            * np.float32(2.0 ** (120 - scale_exp)))
-    vals = np.concatenate([mags, [float(t) for t in ties], [0.0, 1e-38, 1e30], edge]).astype(np.float32)
-    vals = np.concatenate([vals, -vals])
-    assert np.array_equal(device_encode_lo(vals, scale_exp), device_encode(vals, scale_exp))
+    mags = 10.0 ** rng.uniform(-12, 1.0, n) / S * 2.0 ** 8
+    exact = [float(exact_value(c) / Fraction(2) ** scale_exp) for c in (1, 5, 2047, 2048, 12345, 0x7FFE)]
+    vals = np.concatenate([mags, exact, [0.0, 1e-38, 1e30]]).astype(np.float32)
+    return np.concatenate([vals, -vals])
+
+
+@pytest.mark.parametrize("scale_exp", [9, 11, 13])
+def test_stochastic_store_rounds_to_a_neighbouring_code(scale_exp):
+    """For every random draw the stored code is one of the two codes next to the value: the
+    round-to-nearest code or its neighbour on the value's other side (so the error is below one
+    unit); exact codes stay exact, and values beyond the range saturate."""
+    vals = _sr_inputs(scale_exp)
+    rne = device_encode(vals, scale_exp).astype(np.int64)
+    dec_rne = device_decode(rne.astype(np.uint32), scale_exp).astype(np.float64)
+    for k in range(16):
+        got = device_encode_sr(vals, scale_exp, np.full(vals.shape, k)).astype(np.int64)
+        # same sign bit, magnitude code within one of the nearest one, on the value's side
+        assert np.array_equal(got & 0x8000, rne & 0x8000)
+        step = (got & 0x7FFF) - (rne & 0x7FFF)
+        assert np.all(np.abs(step) <= 1)
+        above = np.abs(vals.astype(np.float64)) > np.abs(dec_rne)
+        assert np.all((step >= 0) | ~above) and np.all((step <= 0) | above)
+        assert np.all(step[np.abs(vals.astype(np.float64)) == np.abs(dec_rne)] == 0)
+    big = np.array([1e6, -1e6], dtype=np.float32) / np.float32(2.0 ** scale_exp)
+    assert list(device_encode_sr(big, scale_exp, [15, 15])) == [0x7FFF, 0xFFFF]
+
+
+@pytest.mark.parametrize("scale_exp", [9, 11, 13])
+def test_stochastic_store_is_unbiased(scale_exp):
+    """Averaged over the 16 equally likely draws the decoded value equals the input to within
+    1/32 of a unit (the resolution of 4 random bits; below the smallest normal code the scaled
+    FP32 product is itself rounded on a grid 2^12 finer, which adds up to 2^-13 of a unit), far
+    below round-to-nearest's half unit: rounding errors carry no systematic part."""
+    vals = _sr_inputs(scale_exp, n=4000, seed=7)
+    codes = np.stack([device_encode_sr(vals, scale_exp, np.full(vals.shape, k)) for k in range(16)])
+    mean = device_decode(codes.astype(np.uint32), scale_exp).astype(np.float64).mean(axis=0)
+    # one unit at each value: the spacing of the codes around it
+    rne = device_encode(vals, scale_exp).astype(np.uint32)
+    nxt = device_decode((rne & 0x8000) | np.minimum((rne & 0x7FFF) + 1, 0x7FFF), scale_exp).astype(np.float64)
+    unit = np.abs(nxt - device_decode(rne, scale_exp).astype(np.float64))
+    inrange = (rne & 0x7FFF) < 0x7FFE
+    v = vals.astype(np.float64)
+    assert np.all(np.abs(mean - v)[inrange] <= unit[inrange] * (1 / 32 + 2.0 ** -13))
+    # round-to-nearest, by contrast, is off by up to half a unit for a given value
+    near = device_decode(rne, scale_exp).astype(np.float64)
+    assert (np.abs(near - v)[inrange] / unit[inrange]).max() > 0.4
 
 
 @pytest.mark.parametrize("scale_exp", [9, 11, 13])

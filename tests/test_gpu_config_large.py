@@ -5,14 +5,12 @@ Each storage advances the same channel by 30000 steps (the mean front travels ab
 every 1000 steps the contact line (rho^N = 0 crossing on the two fluid rows next to the walls),
 the tip (crossing on the two centre rows) and the finger length tip - contact line are read on
 the device (lbm_diag_crossings).  Measures against FP64:
-  - tip velocity, the least-squares slope of the tip over the last 10000 steps: within 1 % for
-    FP32 and the 11-bit-fraction 16-bit format (measured 0.001 % and 0.36 %);
-  - finger length at the end: within 1 % for FP32 (measured 0.12 %).  In the 16-bit format the
-    finger (42 nodes long, the difference of two positions near x = 1600) comes out 0.46 nodes
-    longer, 1.09 %: its tip runs 0.36 % fast and leads by 0.41 nodes after 580 nodes of travel,
-    while the contact lines agree to 0.05 nodes.  This misses the 1 % bar at this size and is
-    bounded at 1.5 %; on the sweep's own channels and the 800-wide ones the format stays within
-    1 % (test_gpu_precision, the bench's accuracy record);
+  - tip velocity, the least-squares slope of the tip over the last 10000 steps, and finger length
+    at the end: within 1 % for FP32 and for the 11-bit-fraction 16-bit format (measured 0.001 % /
+    0.12 % for FP32 and 0.015 % / 0.04 % for the 16-bit format, whose stores round
+    stochastically; with round-to-nearest stores the 16-bit tip had run 0.36 % fast and the
+    finger, 42 nodes long, had come out 1.09 % long: a systematic drift that stochastic rounding
+    removes);
   - colour masses (FP64 sums) at the end: printed, and within 1e-3 relative (the inlet injects
     red fluid, so the masses are not conserved; the difference to FP64 is the drift);
   - binary16: reported, and bounded at 3 % like on the small channels.
@@ -70,7 +68,7 @@ def test_fp64_channel_displaces(runs):
     assert 0.5 * U < r["tip_velocity"] < 3.0 * U
 
 
-@pytest.mark.parametrize("storage,bound,len_bound", [("f32", 0.01, 0.01), ("c16", 0.01, 0.015),
+@pytest.mark.parametrize("storage,bound,len_bound", [("f32", 0.01, 0.01), ("c16", 0.01, 0.01),
                                                      ("f16", 0.03, 0.03)])
 def test_reduced_storage_against_fp64(runs, storage, bound, len_bound):
     ref, got = runs["f64"], runs[storage]

@@ -11,8 +11,9 @@ GPU's own step k+1 must agree.
   to 1e-10.
 * The 320-channel sweep in C16 storage: four whole channels (one of each height but one) are
   stepped by the oracle from the decoded state.  The GPU computes in FP32 and rounds the stored
-  deviations to the 16-bit format, so each population must agree within 2^-12 of its
-  deviation from w rho0 (the format's rounding) plus 2e-6 (FP32 arithmetic on O(1) values).
+  deviations to the 16-bit format, so each population must agree within 2^-11 of its
+  deviation from w rho0 (one unit of the format's stochastic rounding) plus 2e-6 (FP32
+  arithmetic on O(1) values).
 """
 import numpy as np
 import pytest
@@ -87,7 +88,7 @@ def test_fullsize_sweep_c16_sampled_channels():
         ref = o.step(1).pops()
         fluid = s.solid == 0
         dev = np.abs(ref.sum(axis=0) - WEIGHTS[:, None, None] * s.params["rho0"] * fluid)
-        tol = dev * 2.0 ** -12 + 2e-6
+        tol = dev * 2.0 ** -11 + 2e-6  # one unit of the stochastically rounded 16-bit store
         err = np.abs(after[d] - ref)
         worst = (err / tol[None]).max()
         print(f"[fullsize] sweep channel {d} ({s.solid.shape[1]} x {s.solid.shape[0]}): "
