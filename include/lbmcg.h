@@ -56,16 +56,17 @@ typedef enum {
  * power-of-two scale per direction (2^9 rest, 2^11 axis, 2^13 diagonal): LBM_STORE_F16 stores
  * binary16, LBM_STORE_C16 a format with one more significand bit (sign, 4-bit exponent with
  * bias 7, 11-bit fraction, subnormals; saturating beyond |deviation| = 2.25 w_alpha rho0).  The
- * step kernels round LBM_STORE_C16 stores stochastically (each value goes to one of its two
+ * step kernels round both 16-bit formats stochastically (each value goes to one of its two
  * neighbouring codes, up with a probability equal to the dropped fraction; error below one
- * unit, 2^-11 relative, with no systematic part; the random bits are a hash of the node's
- * position in its domain and of its state, so a run is reproducible and a domain gives the same
- * results alone or in any batch); the initial upload rounds to nearest.  Colour state is
- * FP64 / FP32.
- * Accuracy against FP64 storage on displacement channels: FP32 and LBM_STORE_C16 keep the finger
- * length within 1 % (16384 x 512 channel, 30000 steps: 0.12 % and 0.04 %); LBM_STORE_F16 does
- * not (measured 0.7-2.6 % off, tip velocity up to 2 %), so runs held to a 1 % finger-length
- * bar should use LBM_STORE_C16. */
+ * unit, 2^-10 relative for binary16 and 2^-11 for LBM_STORE_C16, with no systematic part; the
+ * random bits are a hash of the node's position in its domain and of its state, so a run is
+ * reproducible and a domain gives the same results alone or in any batch); the initial upload
+ * rounds to nearest.  Colour state is FP64 / FP32.
+ * Accuracy against FP64 storage on the 16384 x 512 displacement channel after 30000 steps:
+ * finger length within 0.12 % (FP32), 0.09 % (LBM_STORE_C16) and 0.16 % (LBM_STORE_F16), tip
+ * velocity within 0.02 %.  Capillary filling (Eq. 49) is where the 16-bit formats differ:
+ * meniscus travel within 0.9 % (LBM_STORE_C16) and 1.3 % (LBM_STORE_F16), so runs held to a
+ * 1 % bar should use LBM_STORE_C16. */
 typedef enum {
     LBM_STORE_F64 = 0,
     LBM_STORE_F32 = 1,

@@ -120,6 +120,17 @@ struct Codec<__half> {
     // one mixed-precision FMA (binary16 source, FP32 result); the product is exact
     __device__ static float decode(__half v, int a) { return __builtin_fmaf(__half2float(v), 1.0f / scale(a), 0.0f); }
     __device__ static __half encode(float v, int a) { return __float2half_rn(v * scale(a)); }
+    // The store path's rounding, stochastic as for the 11-bit-fraction format (Codec<C16>): 4
+    // random bits, as an offset k * 512 + 256, are added to the 13 bits of the scaled FP32 value
+    // that binary16 drops, and the conversion truncates (v_cvt_pkrtz), so the magnitude rounds
+    // up with a probability equal to the dropped fraction (to 1/16) wherever binary16 is normal
+    // (below 2^-14 the dropped part is wider and the rounding leans towards zero); values
+    // beyond the largest finite half truncate to it.  The binary16 bits come back in the lower
+    // half of the word.
+    __device__ static uint32_t encode_sr(float v, int a, uint32_t rnd) {
+        const uint32_t b = __float_as_uint(v * scale(a)) + ((((rnd >> (3 * a)) & 15u) << 9) | 0x100u);
+        return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(__uint_as_float(b), 0.0f));
+    }
 };
 
 template <>
@@ -169,10 +180,11 @@ struct Codec<C16> {
     }
 };
 
-// Random bits for the stochastic rounding of one node's 16-bit stores: a hash (multiply and
-// xor-shift rounds) of the node's byte offset within its domain and of the bit pattern of its
-// post-collision rest population, so the bits differ from node to node and from step to step,
-// and a domain's results do not depend on the tile shape or on the other domains of its batch.
+// Random bits for the stochastic rounding of one node's stores in either 16-bit format: a hash
+// (multiply and xor-shift rounds) of the node's byte offset within its domain and of the bit
+// pattern of its post-collision rest population, so the bits differ from node to node and from
+// step to step, and a domain's results do not depend on the tile shape or on the other domains
+// of its batch.
 __device__ __forceinline__ uint32_t round_bits(uint32_t node_bytes, float v) {
     uint32_t h = (node_bytes ^ __float_as_uint(v)) * 0x9E3779B1u;
     h ^= h >> 16;
@@ -539,11 +551,11 @@ struct Buf<C16> {
     __device__ static void store(Rsrc r, uint32_t vo, uint32_t so, C16 v) {
         __builtin_amdgcn_raw_buffer_store_b16(v.bits, r, vo, so, 0);
     }
-    // store the lower half of a word (the form Codec<C16>::encode_sr returns)
-    __device__ static void store_lo(Rsrc r, uint32_t vo, uint32_t so, uint32_t w) {
-        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)w, r, vo, so, 0);
-    }
 };
+// Store the lower half of a word (the form the 16-bit encode_sr functions return).
+__device__ __forceinline__ void store_lo16(Rsrc r, uint32_t vo, uint32_t so, uint32_t w) {
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)w, r, vo, so, 0);
+}
 template <>
 struct Buf<uint16_t> {
     __device__ static uint16_t load(Rsrc r, uint32_t vo, uint32_t so) {
@@ -725,11 +737,11 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     };
     // one row of outputs: populations, then the colour state (c, vx, vy)
     auto store_row = [&](uint32_t vf, uint32_t vc, const AT (&o)[9], AT c, AT bx, AT by) {
-        const uint32_t rb = std::is_same_v<T, C16> ? round_bits(vf - (uint32_t)D.off * SB, o[0]) : 0u;
+        const uint32_t rb = sizeof(T) == 2 ? round_bits(vf - (uint32_t)D.off * SB, o[0]) : 0u;
 #pragma unroll
         for (int a = 0; a < 9; a++) {
-            if constexpr (std::is_same_v<T, C16>)
-                Buf<C16>::store_lo(f_out, vf, (uint32_t)a * FP, Codec<C16>::encode_sr(o[a], a, rb));
+            if constexpr (sizeof(T) == 2)
+                store_lo16(f_out, vf, (uint32_t)a * FP, Codec<T>::encode_sr(o[a], a, rb));
             else
                 Buf<T>::store(f_out, vf, (uint32_t)a * FP, Codec<T>::encode(o[a], a));
         }
@@ -1072,9 +1084,9 @@ struct PairIO<__half> {
         lo = Codec<__half>::decode(__ushort_as_half((unsigned short)(v & 0xFFFFu)), a);
         hi = Codec<__half>::decode(__ushort_as_half((unsigned short)(v >> 16)), a);
     }
-    __device__ static V encode(float lo, float hi, int a, uint32_t, uint32_t) {
-        return (uint32_t)__half_as_ushort(Codec<__half>::encode(lo, a)) |
-               ((uint32_t)__half_as_ushort(Codec<__half>::encode(hi, a)) << 16);
+    // stochastic rounding as in step_kernel, with each node's own random bits
+    __device__ static V encode(float lo, float hi, int a, uint32_t rlo, uint32_t rhi) {
+        return (Codec<__half>::encode_sr(lo, a, rlo) & 0xFFFFu) | (Codec<__half>::encode_sr(hi, a, rhi) << 16);
     }
     __device__ static V zero() { return 0u; }
 };
@@ -1574,8 +1586,8 @@ __global__ __launch_bounds__(TILE_LANES *R, 2) void pair_kernel(const StepArgs<T
             const bool st = out[0] && row_out;
             const uint32_t vf = st ? nd * SB : NOWHERE, vc = st ? nd * CB : NOWHERE;
             const uint32_t vl = vf - (uint32_t)D.off * SB;  // offset within the domain
-            const uint32_t rb0 = std::is_same_v<T, C16> ? round_bits(vl, o[0][0]) : 0u;
-            const uint32_t rb1 = std::is_same_v<T, C16> ? round_bits(vl + SB, o[1][0]) : 0u;
+            const uint32_t rb0 = sizeof(T) == 2 ? round_bits(vl, o[0][0]) : 0u;
+            const uint32_t rb1 = sizeof(T) == 2 ? round_bits(vl + SB, o[1][0]) : 0u;
 #pragma unroll
             for (int a = 0; a < 9; a++)
                 IO::store(f_out, vf, (uint32_t)a * FP, IO::encode(o[0][a], o[1][a], a, rb0, rb1));

@@ -13,7 +13,8 @@ the device (lbm_diag_crossings).  Measures against FP64:
     removes);
   - colour masses (FP64 sums) at the end: printed, and within 1e-3 relative (the inlet injects
     red fluid, so the masses are not conserved; the difference to FP64 is the drift);
-  - binary16: reported, and bounded at 3 % like on the small channels.
+  - binary16, also with stochastically rounded stores: within 1 % as well (measured 0.017 % tip
+    velocity, 0.16 % finger length; with round-to-nearest stores 0.72 % and 2.58 %).
 """
 import numpy as np
 import pytest
@@ -69,7 +70,7 @@ def test_fp64_channel_displaces(runs):
 
 
 @pytest.mark.parametrize("storage,bound,len_bound", [("f32", 0.01, 0.01), ("c16", 0.01, 0.01),
-                                                     ("f16", 0.03, 0.03)])
+                                                     ("f16", 0.01, 0.01)])
 def test_reduced_storage_against_fp64(runs, storage, bound, len_bound):
     ref, got = runs["f64"], runs[storage]
     d_len = abs(got["length"][-1] - ref["length"][-1]) / abs(ref["length"][-1])

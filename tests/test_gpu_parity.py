@@ -185,12 +185,12 @@ def test_checkpoint_roundtrip_is_bitwise():
 def test_reduced_storage_one_step_from_gpu_state(storage):
     """The FP32-arithmetic paths, one step at a time: after 30 steps the GPU state is read back,
     the oracle advances it by one step, and the GPU's own next step must agree within the
-    storage's rounding of each population's deviation from w rho0 (2^-22 for FP32, 2^-11 for
-    binary16, one unit, 2^-11, for the 11-bit-fraction format, whose stores round
-    stochastically) plus 2e-6 for FP32 arithmetic, on channels
+    storage's rounding of each population's deviation from w rho0 (2^-22 for FP32; one unit for
+    the 16-bit formats, whose stores round stochastically: 2^-10 for binary16, 2^-11 for the
+    11-bit-fraction format) plus 2e-6 for FP32 arithmetic, on channels
     (walls, inlet, outlet, bounce-back, wetting), a flat-wall droplet and a cylinder."""
     weights = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
-    rel = {"f32": 2.0 ** -22, "f16": 2.0 ** -11, "c16": 2.0 ** -11}[storage]
+    rel = {"f32": 2.0 ** -22, "f16": 2.0 ** -10, "c16": 2.0 ** -11}[storage]
     setups = [W.fingering_channel(nx=300, h=75, x_interface=150.0, M=10.0, theta_deg=60.0,
                                   ca=0.1, nu_r=0.5, sigma=0.05, name="c75"),
               W.fingering_channel(nx=260, h=50, x_interface=100.0, M=2.0, theta_deg=120.0,

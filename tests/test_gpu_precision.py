@@ -5,12 +5,13 @@ fraction, both with per-direction power-of-two scales, FP32 colour state and ari
 reproduce the FP64 path's physics:
   - static contact angle (the Table I flat-wall droplets, and droplets on a cylinder with
     staircase and analytic wall normals) within 0.5 degrees;
-  - finger length of a displacement channel (tip minus contact line) within 1 %;
-  - distance travelled by a capillary-filling meniscus (Eq. 49) within 1 % (binary16: 3 %);
+  - finger length of a displacement channel (tip minus contact line) within 1 %, and the tip
+    velocity over the last 2000 steps within 1 % (measured, with the 16-bit stores rounded
+    stochastically: at most 0.01 % in every storage; with round-to-nearest stores binary16 had
+    been 0.7-1.6 % short and up to 2 % slow);
+  - distance travelled by a capillary-filling meniscus (Eq. 49) within 1 % (binary16: 3 %,
+    measured 1.3 %);
   - the spurious-velocity level |u|max of static droplets within 1 % (FP32) or 10 % (16-bit).
-The tip velocity over the last 2000 steps of the finger runs is within 1 % of the FP64 one for
-FP32 and c16 storage (measured: 0.00 % and up to 0.26 %); binary16 is reported and bounded at
-3 % (measured: up to 2.0 %), like its finger length.
 Colour-mass drift is printed for the record and only bounded loosely: the FP64 path conserves
 it to rounding (tests/test_gpu_parity.py), the reduced paths round every stored population.
 """
@@ -164,7 +165,7 @@ def test_contact_angle_within_half_degree_of_fp64(droplet_runs, storage):
     assert drift.max() < (1e-4 if storage == "f32" else 1e-2)
 
 
-@pytest.mark.parametrize("storage", ["f32", "c16"])
+@pytest.mark.parametrize("storage", ["f32", "c16", "f16"])
 def test_finger_length_within_one_percent_of_fp64(finger_runs, storage):
     for (M, th, ca), m64, m in zip(FINGERS, finger_runs["f64"], finger_runs[storage]):
         assert m64["length"] is not None and m["length"] is not None
@@ -173,7 +174,7 @@ def test_finger_length_within_one_percent_of_fp64(finger_runs, storage):
                              f"f64 {m64['length']:.3f} ({100 * rel:.2f} %)")
 
 
-@pytest.mark.parametrize("storage,bound", [("f32", 0.01), ("c16", 0.01), ("f16", 0.03)])
+@pytest.mark.parametrize("storage,bound", [("f32", 0.01), ("c16", 0.01), ("f16", 0.01)])
 def test_tip_velocity_against_fp64(finger_runs, storage, bound):
     for (M, th, ca), m64, m in zip(FINGERS, finger_runs["f64"], finger_runs[storage]):
         rel = abs(m["tip_velocity"] - m64["tip_velocity"]) / abs(m64["tip_velocity"])
@@ -184,11 +185,12 @@ def test_tip_velocity_against_fp64(finger_runs, storage, bound):
 
 
 def test_binary16_finger_length_error_is_reported(finger_runs):
-    """binary16 storage: the finger-length deviation from FP64 is recorded, bounded at 3 %."""
+    """binary16 storage: the finger-length deviation from FP64 is recorded (and held to 1 % by
+    test_finger_length_within_one_percent_of_fp64)."""
     for (M, th, ca), m64, m in zip(FINGERS, finger_runs["f64"], finger_runs["f16"]):
         rel = abs(m["length"] - m64["length"]) / abs(m64["length"])
         print(f"[precision] f16 finger M={M} theta={th} Ca={ca}: {100 * rel:.2f} %", flush=True)
-        assert rel <= 0.03
+        assert rel <= 0.01
 
 
 def test_c16_initial_state_round_trip():
