@@ -63,10 +63,10 @@ typedef enum {
  * reproducible and a domain gives the same results alone or in any batch); the initial upload
  * rounds to nearest.  Colour state is FP64 / FP32.
  * Accuracy against FP64 storage on the 16384 x 512 displacement channel after 30000 steps:
- * finger length within 0.12 % (FP32), 0.09 % (LBM_STORE_C16) and 0.16 % (LBM_STORE_F16), tip
- * velocity within 0.02 %.  Capillary filling (Eq. 49) is where the 16-bit formats differ:
- * meniscus travel within 0.9 % (LBM_STORE_C16) and 1.3 % (LBM_STORE_F16), so runs held to a
- * 1 % bar should use LBM_STORE_C16. */
+ * finger length within 0.12 % (FP32), 0.001 % (LBM_STORE_C16) and 0.21 % (LBM_STORE_F16), tip
+ * velocity within 0.005 %.  Capillary filling (Eq. 49) is where the 16-bit formats differ:
+ * meniscus travel within 0.8 % (LBM_STORE_C16) and 1.0-1.3 % (LBM_STORE_F16), so runs held to
+ * a 1 % bar should use LBM_STORE_C16. */
 typedef enum {
     LBM_STORE_F64 = 0,
     LBM_STORE_F32 = 1,

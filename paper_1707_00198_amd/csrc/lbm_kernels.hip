@@ -120,15 +120,15 @@ struct Codec<__half> {
     // one mixed-precision FMA (binary16 source, FP32 result); the product is exact
     __device__ static float decode(__half v, int a) { return __builtin_fmaf(__half2float(v), 1.0f / scale(a), 0.0f); }
     __device__ static __half encode(float v, int a) { return __float2half_rn(v * scale(a)); }
-    // The store path's rounding, stochastic as for the 11-bit-fraction format (Codec<C16>): 4
-    // random bits, as an offset k * 512 + 256, are added to the 13 bits of the scaled FP32 value
-    // that binary16 drops, and the conversion truncates (v_cvt_pkrtz), so the magnitude rounds
-    // up with a probability equal to the dropped fraction (to 1/16) wherever binary16 is normal
-    // (below 2^-14 the dropped part is wider and the rounding leans towards zero); values
-    // beyond the largest finite half truncate to it.  The binary16 bits come back in the lower
-    // half of the word.
+    // The store path's rounding, stochastic as for the 11-bit-fraction format (Codec<C16>): a
+    // uniform random 13-bit offset (bits 2a .. 2a + 12 of rnd) is added to the 13 bits of the
+    // scaled FP32 value that binary16 drops, and the conversion truncates (v_cvt_pkrtz), so the
+    // magnitude rounds up with a probability equal to the dropped fraction wherever binary16 is
+    // normal (below 2^-14 the dropped part is wider and the rounding leans towards zero);
+    // values beyond the largest finite half truncate to it.  The binary16 bits come back in the
+    // lower half of the word.
     __device__ static uint32_t encode_sr(float v, int a, uint32_t rnd) {
-        const uint32_t b = __float_as_uint(v * scale(a)) + ((((rnd >> (3 * a)) & 15u) << 9) | 0x100u);
+        const uint32_t b = __float_as_uint(v * scale(a)) + __builtin_amdgcn_ubfe(rnd, 2 * a, 13);
         return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(__uint_as_float(b), 0.0f));
     }
 };
@@ -164,32 +164,35 @@ struct Codec<C16> {
     }
     // The store path's rounding: stochastic, so that rounding errors carry no systematic part
     // that could add up over many steps (with round-to-nearest the 16384 x 512 displacement
-    // channel's finger tip ran 0.36 % fast over 30000 steps; with this rounding 0.015 %).  The
+    // channel's finger tip ran 0.36 % fast over 30000 steps; with this rounding 0.02 %).  The
     // scaled value is clamped to the largest code while still an FP32 number (0x07FFF000 as
-    // bits, so no carry can reach the unused exponent bits), then 4 random bits, as an offset
-    // k * 256 + 128 (mean: half a unit), are added to the 12 bits that the code drops: the
-    // magnitude rounds up with a probability equal to the dropped fraction to within 1/16, and
-    // the sign is carried over.  The result is one of the two codes next to the value (exact
-    // values stay exact), in the lower 16 bits of the word (the upper bits undefined).  rnd
-    // supplies bits 3a .. 3a + 3 for direction a.
+    // bits, so no carry can reach the unused exponent bits), then a uniform random 12-bit
+    // offset is added to the 12 bits that the code drops: the magnitude rounds up with a
+    // probability equal to the dropped fraction, and the sign is carried over.  The result is
+    // one of the two codes next to the value (exact values stay exact), in the lower 16 bits of
+    // the word (the upper bits undefined).  The offset is bits 2a .. 2a + 11 of rnd for
+    // direction a (one bit-field extract, as round-to-nearest needs one for its tie bit).
     __device__ static uint32_t encode_sr(float v, int a, uint32_t rnd) {
         constexpr float top = 0x1.fffp-112f;  // bits 0x07FFF000
         const float x = __builtin_amdgcn_fmed3f(v * enc(a), -top, top);
-        const uint32_t t = __float_as_uint(x) + ((((rnd >> (3 * a)) & 15u) << 8) | 0x80u);
+        const uint32_t t = __float_as_uint(x) + __builtin_amdgcn_ubfe(rnd, 2 * a, 12);
         return (t >> 12) | ((t >> 16) & 0x8000u);
     }
 };
 
 // Random bits for the stochastic rounding of one node's stores in either 16-bit format: a hash
-// (multiply and xor-shift rounds) of the node's byte offset within its domain and of the bit
-// pattern of its post-collision rest population, so the bits differ from node to node and from
-// step to step, and a domain's results do not depend on the tile shape or on the other domains
-// of its batch.
+// of the node's byte offset within its domain and of the bit pattern of its post-collision rest
+// population, so the bits differ from node to node and from step to step, and a domain's
+// results do not depend on the tile shape or on the other domains of its batch.  Two rounds of
+// xor-shift and a 24-bit multiply (full-rate v_mul_u32_u24, where a 32-bit multiply issues at
+// a quarter of the rate); the xor-shift before each multiply folds the upper bits in.
 __device__ __forceinline__ uint32_t round_bits(uint32_t node_bytes, float v) {
-    uint32_t h = (node_bytes ^ __float_as_uint(v)) * 0x9E3779B1u;
-    h ^= h >> 16;
-    h *= 0x7FEB352Du;
-    return h ^ (h >> 15);
+    uint32_t x = node_bytes ^ __float_as_uint(v);
+    x ^= x >> 16;
+    uint32_t h = __umul24(x, 0x9E3779u);
+    h ^= h >> 13;
+    h = __umul24(h, 0x85EBCAu);
+    return h ^ (h >> 16);
 }
 
 // Periodic wrap of an index that is usually already in [0, n): one compare on the fast path.

@@ -63,15 +63,15 @@ def device_encode(v, scale_exp):
     return (r | ((t >> 16) & 0x8000)).astype(np.uint16)
 
 
-def device_encode_sr(v, scale_exp, k):
+def device_encode_sr(v, scale_exp, r):
     """numpy model of the step kernels' stochastic-rounding store: the scaled FP32 value clamped
-    to +-0x07FFF000 (as bits) by a median of three, the random offset k * 256 + 128 (k: 4 random
-    bits) added to the 12 dropped bits of the signed word, the sign moved to bit 15; the lower
-    16 bits are stored."""
+    to +-0x07FFF000 (as bits) by a median of three, a random 12-bit offset r (0 .. 4095) added to
+    the 12 dropped bits of the signed word, the sign moved to bit 15; the lower 16 bits are
+    stored."""
     x = np.asarray(v, dtype=np.float32) * np.float32(2.0 ** (scale_exp - 120))
     top = np.uint32(0x07FFF000).view(np.float32)
     x = np.clip(x, -top, top)
-    t = x.view(np.uint32) + ((np.asarray(k, dtype=np.uint32) & np.uint32(15)) << np.uint32(8)) + np.uint32(0x80)
+    t = x.view(np.uint32) + (np.asarray(r, dtype=np.uint32) & np.uint32(0xFFF))
     return ((t >> 12) | ((t >> 16) & np.uint32(0x8000))).astype(np.uint16)
 
 
@@ -86,42 +86,41 @@ def _sr_inputs(scale_exp, n=20000, seed=2024):
 
 @pytest.mark.parametrize("scale_exp", [9, 11, 13])
 def test_stochastic_store_rounds_to_a_neighbouring_code(scale_exp):
-    """For every random draw the stored code is one of the two codes next to the value: the
+    """For every random offset the stored code is one of the two codes next to the value: the
     round-to-nearest code or its neighbour on the value's other side (so the error is below one
     unit); exact codes stay exact, and values beyond the range saturate."""
     vals = _sr_inputs(scale_exp)
     rne = device_encode(vals, scale_exp).astype(np.int64)
     dec_rne = device_decode(rne.astype(np.uint32), scale_exp).astype(np.float64)
-    for k in range(16):
-        got = device_encode_sr(vals, scale_exp, np.full(vals.shape, k)).astype(np.int64)
+    above = np.abs(vals.astype(np.float64)) > np.abs(dec_rne)
+    for r in (0, 1, 127, 2047, 2048, 3000, 4094, 4095):
+        got = device_encode_sr(vals, scale_exp, np.full(vals.shape, r)).astype(np.int64)
         # same sign bit, magnitude code within one of the nearest one, on the value's side
         assert np.array_equal(got & 0x8000, rne & 0x8000)
         step = (got & 0x7FFF) - (rne & 0x7FFF)
         assert np.all(np.abs(step) <= 1)
-        above = np.abs(vals.astype(np.float64)) > np.abs(dec_rne)
         assert np.all((step >= 0) | ~above) and np.all((step <= 0) | above)
         assert np.all(step[np.abs(vals.astype(np.float64)) == np.abs(dec_rne)] == 0)
     big = np.array([1e6, -1e6], dtype=np.float32) / np.float32(2.0 ** scale_exp)
-    assert list(device_encode_sr(big, scale_exp, [15, 15])) == [0x7FFF, 0xFFFF]
+    assert list(device_encode_sr(big, scale_exp, [4095, 4095])) == [0x7FFF, 0xFFFF]
 
 
 @pytest.mark.parametrize("scale_exp", [9, 11, 13])
 def test_stochastic_store_is_unbiased(scale_exp):
-    """Averaged over the 16 equally likely draws the decoded value equals the input to within
-    1/32 of a unit (the resolution of 4 random bits; below the smallest normal code the scaled
-    FP32 product is itself rounded on a grid 2^12 finer, which adds up to 2^-13 of a unit), far
-    below round-to-nearest's half unit: rounding errors carry no systematic part."""
-    vals = _sr_inputs(scale_exp, n=4000, seed=7)
-    codes = np.stack([device_encode_sr(vals, scale_exp, np.full(vals.shape, k)) for k in range(16)])
+    """Averaged over all 4096 equally likely offsets the decoded value equals the input (below
+    the smallest normal code the scaled FP32 product is itself rounded on a grid 2^12 finer,
+    which leaves up to 2^-13 of a unit), where round-to-nearest is off by up to half a unit:
+    rounding errors carry no systematic part."""
+    vals = _sr_inputs(scale_exp, n=300, seed=7)
+    offsets = np.arange(4096, dtype=np.uint32)
+    codes = device_encode_sr(vals[None, :], scale_exp, offsets[:, None])
     mean = device_decode(codes.astype(np.uint32), scale_exp).astype(np.float64).mean(axis=0)
-    # one unit at each value: the spacing of the codes around it
     rne = device_encode(vals, scale_exp).astype(np.uint32)
     nxt = device_decode((rne & 0x8000) | np.minimum((rne & 0x7FFF) + 1, 0x7FFF), scale_exp).astype(np.float64)
     unit = np.abs(nxt - device_decode(rne, scale_exp).astype(np.float64))
     inrange = (rne & 0x7FFF) < 0x7FFE
     v = vals.astype(np.float64)
-    assert np.all(np.abs(mean - v)[inrange] <= unit[inrange] * (1 / 32 + 2.0 ** -13))
-    # round-to-nearest, by contrast, is off by up to half a unit for a given value
+    assert np.all(np.abs(mean - v)[inrange] <= unit[inrange] * 2.0 ** -13 * (1 + 1e-6) + 1e-300)
     near = device_decode(rne, scale_exp).astype(np.float64)
     assert (np.abs(near - v)[inrange] / unit[inrange]).max() > 0.4
 

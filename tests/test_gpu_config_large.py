@@ -7,14 +7,14 @@ the tip (crossing on the two centre rows) and the finger length tip - contact li
 the device (lbm_diag_crossings).  Measures against FP64:
   - tip velocity, the least-squares slope of the tip over the last 10000 steps, and finger length
     at the end: within 1 % for FP32 and for the 11-bit-fraction 16-bit format (measured 0.001 % /
-    0.12 % for FP32 and 0.015 % / 0.04 % for the 16-bit format, whose stores round
+    0.12 % for FP32 and 0.003 % / 0.001 % for the 16-bit format, whose stores round
     stochastically; with round-to-nearest stores the 16-bit tip had run 0.36 % fast and the
     finger, 42 nodes long, had come out 1.09 % long: a systematic drift that stochastic rounding
     removes);
   - colour masses (FP64 sums) at the end: printed, and within 1e-3 relative (the inlet injects
     red fluid, so the masses are not conserved; the difference to FP64 is the drift);
-  - binary16, also with stochastically rounded stores: within 1 % as well (measured 0.017 % tip
-    velocity, 0.16 % finger length; with round-to-nearest stores 0.72 % and 2.58 %).
+  - binary16, also with stochastically rounded stores: within 1 % as well (measured 0.004 % tip
+    velocity, 0.21 % finger length; with round-to-nearest stores 0.72 % and 2.58 %).
 """
 import numpy as np
 import pytest
