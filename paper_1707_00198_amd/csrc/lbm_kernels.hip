@@ -119,7 +119,6 @@ struct Codec<__half> {
     __device__ static float load(const __half *p, int a) { return __half2float(*p) * (1.0f / scale(a)); }
     // one mixed-precision FMA (binary16 source, FP32 result); the product is exact
     __device__ static float decode(__half v, int a) { return __builtin_fmaf(__half2float(v), 1.0f / scale(a), 0.0f); }
-    __device__ static __half encode(float v, int a) { return __float2half_rn(v * scale(a)); }
     // The store path's rounding, stochastic as for the 11-bit-fraction format (Codec<C16>): a
     // uniform random 13-bit offset (bits 2a .. 2a + 12 of rnd) is added to the 13 bits of the
     // scaled FP32 value that binary16 drops, and the conversion truncates (v_cvt_pkrtz), so the
@@ -151,17 +150,6 @@ struct Codec<C16> {
         return __uint_as_float(((u & 0x7FFFu) << 12) | ((u & 0x8000u) << 16)) * dec(a);
     }
     __device__ static float load(const C16 *p, int a) { return decode(*p, a); }
-    // The inverse map: the same FP32 word, rounded to 11 fraction bits (to nearest, ties to
-    // even; a carry moves into the exponent), saturating at the largest finite value.  Below
-    // the smallest normal the scaling product is an FP32 subnormal, rounded first on a grid
-    // 2^12 times finer: within 2^-12 of a halfway point that result can differ by one unit
-    // from a single rounding.
-    __device__ static C16 encode(float v, int a) {
-        const uint32_t b = __float_as_uint(v * enc(a));
-        const uint32_t mag = b & 0x7FFFFFFFu;
-        const uint32_t r = min((mag + 0x7FFu + ((mag >> 12) & 1u)) >> 12, 0x7FFFu);
-        return C16{(uint16_t)(r | ((b >> 16) & 0x8000u))};
-    }
     // The store path's rounding: stochastic, so that rounding errors carry no systematic part
     // that could add up over many steps (with round-to-nearest the 16384 x 512 displacement
     // channel's finger tip ran 0.36 % fast over 30000 steps; with this rounding 0.02 %).  The
@@ -1141,6 +1129,7 @@ __device__ __forceinline__ long long pull_elem(const Nbr &nb, int x, uint32_t m,
 constexpr int PAIR_HALO = 6;                          // halo columns per side (even)
 constexpr int PAIR_COLS = 2 * TILE_LANES;             // window columns
 constexpr int PAIR_OUT = PAIR_COLS - 2 * PAIR_HALO;   // output columns of a window
+static_assert(PAIR_OUT == 2 * TILE_LANES - 12, "the host's tile_out(cols, 2) strides strips by the pair window's outputs");
 
 template <class T, int R, bool WV>
 __global__ __launch_bounds__(TILE_LANES *R, 2) void pair_kernel(const StepArgs<T, float> A) {

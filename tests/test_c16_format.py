@@ -1,11 +1,13 @@
 """The 16-bit population format of LBM_STORE_C16 (include/lbmcg.h), checked on the CPU.
 
 The format: sign, 4-bit exponent e with bias 7, 11-bit fraction f; value 2^(e-7) (1 + f/2^11)
-for e >= 1 and 2^-6 f/2^11 for e = 0.  The device codec computes it with FP32 bit operations
-(the exponent-and-fraction bits shifted into an FP32 word, then one multiplication).  Here a
-numpy model of those bit operations is compared with the format's definition evaluated in exact
-rational arithmetic (round to nearest, ties to even), so that an off-by-one shift, a wrong
-rounding bias or a lost subnormal in the bit trick fails a test.
+for e >= 1 and 2^-6 f/2^11 for e = 0.  The device decodes it with FP32 bit operations (the
+exponent-and-fraction bits shifted into an FP32 word, then one multiplication) and stores it
+with stochastic rounding.  Here numpy models of those bit operations are compared with the
+format's definition evaluated in exact rational arithmetic, so that an off-by-one shift, a wrong
+rounding bias or a lost subnormal in the bit trick fails a test.  Round-to-nearest (ties to
+even) is the format's nominal rounding, the one the host applies to the initial state; its
+bit model below is the reference the stochastic store is checked against.
 """
 from fractions import Fraction
 
@@ -56,7 +58,8 @@ def device_decode(bits, scale_exp):
 
 
 def device_encode(v, scale_exp):
-    """numpy model of the device encode (FP32 multiply, integer round-to-nearest-even)."""
+    """Round-to-nearest-even to the format by FP32 bit operations (FP32 multiply, integer
+    increment of the magnitude); checked against the exact definition below."""
     t = (np.asarray(v, dtype=np.float32) * np.float32(2.0 ** (scale_exp - 120))).view(np.uint32)
     mag = t & np.uint32(0x7FFFFFFF)
     r = np.minimum((mag + np.uint32(0x7FF) + ((mag >> 12) & 1)) >> 12, 0x7FFF)
