@@ -21,6 +21,11 @@ HIPCC_FLAGS = [
 ]
 
 
+EXAMPLE_SRC = os.path.join(CSRC, "c_api_example.c")
+EXAMPLE = os.path.join(PKG, "lbm_c_example")
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+
+
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
@@ -29,7 +34,22 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_example(verbose)
     return LIB
+
+
+def build_example(verbose: bool = False) -> str:
+    """The C example of the interface (plain C99 with gcc, linked against liblbmcg.so found next
+    to it and the HIP runtime)."""
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(os.path.dirname(ROCM_LIB), "include"), "-I", INCLUDE,
+           "-o", EXAMPLE + ".tmp", EXAMPLE_SRC, "-L", PKG, "-llbmcg", "-L", ROCM_LIB, "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + ROCM_LIB]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(EXAMPLE + ".tmp", EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":

@@ -182,3 +182,19 @@ def test_library_classification_matches_oracle(idx):
     o = oracle.Oracle(s.solid, s.rho_r0, s.rho_b0, **s.oracle_kwargs())
     assert np.array_equal(cls, o.classes())
     assert np.array_equal(nrm, o.wall_normals())
+
+
+def test_c_example_is_built_and_reports_a_missing_device():
+    """The plain-C driver of the interface (csrc/c_api_example.c) is built with the library; it
+    rejects a bad storage name before touching HIP, and without a usable device it says so and
+    exits with status 2 instead of crashing."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_1707_00198_amd", "lbm_c_example")
+    assert os.path.exists(exe), "built by __graft_entry__.build()"
+    r = subprocess.run([exe, "f128"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage" in r.stderr
+    import torch
+    if torch.cuda.is_available():
+        return
+    r = subprocess.run([exe, "f64", "1"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2 and "no HIP device" in r.stderr
