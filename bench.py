@@ -6,9 +6,9 @@ bounce-back and open boundaries, wetting boundary, curvature/force, MRT collisio
 store).  Inputs are resident in HBM before timing starts.
 
 Default headline: the batched fingering sweep (320 channels, H in {50,75,100,150,200}, L = 16H,
-M x Ca x theta factorial) with 16-bit populations (the C16 format: sign, 4-bit exponent, 11-bit
-fraction, per-direction power-of-two scales; it meets the reduced-precision accuracy bar, which
-IEEE binary16 misses on the finger length) and FP32 arithmetic, timed in the form the sweep is
+M x Ca x theta factorial) with populations stored as IEEE binary16 deviations from the weights
+(per-direction power-of-two scales, stochastically rounded stores) and FP32 arithmetic; ``--storage
+c16`` selects the 16-bit format with one more fraction bit.  Timed in the form the sweep is
 meant to run: the autotuned tile shape, steps replayed as HIP graphs.  The same JSON line
 reports the sweep with the built-in shape launched step by step, the plain FP64 single-domain
 throughput on the 16384 x 512 fingering channel and the ratio of the two, the accuracy of the
@@ -96,7 +96,7 @@ def copy_calibration():
 def build_workload(name):
     from paper_1707_00198_amd import workloads as W
     if name == "sweep":
-        return W.cfg_sweep(), "c16", ("batched fingering sweep: 320 channels, H in {50,75,100,150,200}"
+        return W.cfg_sweep(), "f16", ("batched fingering sweep: 320 channels, H in {50,75,100,150,200}"
                                       " (64 each), L = 16H, M x Ca x theta factorial, one launch per step")
     if name == "fingering_large":
         return [W.cfg_fingering_large()], "f64", "fingering channel 16384 x 512, M = 50, theta = 30 deg"
