@@ -126,6 +126,17 @@ def test_parity_fp64_1000_steps_fingering_crop():
     assert_parity(g, r, what="fingering crop 1000 steps")
 
 
+def test_parity_fp64_1000_steps_fingering_full_size():
+    """The 2000 x 100 fingering channel at its full size (M = 10, theta = 60 deg, inlet at x = 0,
+    convective outlet, interface at x = 200), 1000 steps in the built-in launch configuration."""
+    s = W.cfg_fingering()
+    lat = lattice([s])
+    print(f"tile {lat.tile}", flush=True)
+    g = lat.step(1000).pops(0)
+    r = oracle_for(s).step(1000).pops()
+    assert_parity(g, r, what="fingering 2000 x 100, 1000 steps")
+
+
 def test_parity_fp64_1000_steps_cylinder():
     s = W.cylinder_droplet(n=200, rc=40.0, rd=40.0, theta_deg=60.0, ccx=100.0, ccy=60.0,
                            dcx_offset=0.37)
