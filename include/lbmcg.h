@@ -192,8 +192,9 @@ int64_t lbm_steps_taken(const lbm_ctx *ctx);
 /* Tile shape of the fused step: `chunk_rows` rows of a strip per work item (multiple of 4,
  * >= 8; 0 = built-in choice), `waves` tile rows advanced per iteration (4 or 8; 0 = built-in),
  * `cols` wavefronts side by side in a tile row and `cols_per_lane` node columns per lane:
- *   cols 1, cols_per_lane 1: 64-column tiles with 54 output columns;
- *   cols 2, cols_per_lane 1: 128-column tiles with 118 output columns (8 x 2 not provided);
+ *   cols 1, cols_per_lane 1: 64-column tiles with 56 output columns (54 for LBM_STORE_F64);
+ *   cols 2, cols_per_lane 1: 128-column tiles with 120 output columns (118 for LBM_STORE_F64;
+ *     8 x 2 not provided);
  *   cols 1, cols_per_lane 2: 128-column tiles with 116 output columns, each lane updating two
  *     adjacent nodes; only for the FP32-arithmetic storages and batches whose domains all have an
  *     even nx (never the built-in choice; lbm_autotune weighs it).

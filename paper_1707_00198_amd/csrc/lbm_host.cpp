@@ -64,8 +64,8 @@ struct Layout {
            mass_out = 0, flag = 0, scratch_bytes = 0;
 };
 
-int strips_of(const lbm_domain_desc &d, int cols = 1, int npl = 1) {
-    return (d.nx + tile_out(cols, npl) - 1) / tile_out(cols, npl);
+int strips_of(const lbm_domain_desc &d, int cols, int npl, int storage) {
+    return (d.nx + tile_out(cols, npl, storage) - 1) / tile_out(cols, npl, storage);
 }
 
 Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
@@ -74,7 +74,7 @@ Layout make_layout(const lbm_domain_desc *d, int n, int storage) {
     for (int i = 0; i < n; i++) {
         nodes += align_up((size_t)d[i].nx * d[i].ny, 64);
         rows += d[i].ny;
-        cap += (size_t)strips_of(d[i]) * ((d[i].ny + 7) / 8);
+        cap += (size_t)strips_of(d[i], 1, 1, 0) * ((d[i].ny + 7) / 8);  // the narrowest strips
     }
     L.plane = align_up(std::max<size_t>(nodes, 64), 128);
     L.rows = rows;
@@ -388,17 +388,18 @@ AnyArgs make_diag_args(const lbm_ctx *c, int cl_dom = -1) {
 // stream a narrow band of every plane, which measured markedly faster than a strip at a time.
 // A domain with more items than one run is cut into strip groups of about one run each, so
 // that every XCD works through a compact region and neighbouring strips share its L2.
-std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk, int cols, int npl) {
+std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chunk, int cols, int npl,
+                                  int storage) {
     size_t total = 0;
     for (const auto &q : d) {
         const int nch = std::max(1, (q.ny + chunk - 1) / chunk);
-        total += (size_t)strips_of(q, cols, npl) * nch;
+        total += (size_t)strips_of(q, cols, npl, storage) * nch;
     }
     const size_t run = std::max<size_t>(1, total / 8);
     std::vector<WorkItem> out;
     out.reserve(total);
     for (int i = 0; i < (int)d.size(); i++) {
-        const int ny = d[i].ny, S = strips_of(d[i], cols, npl);
+        const int ny = d[i].ny, S = strips_of(d[i], cols, npl, storage);
         const int nch = std::max(1, (ny + chunk - 1) / chunk);
         const int ch = ((ny + nch - 1) / nch + 3) / 4 * 4;
         const size_t items = (size_t)S * nch;
@@ -408,7 +409,7 @@ std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chu
             for (int k = 0; k < nch; k++) {
                 const int y0 = k * ch, y1 = std::min(ny, y0 + ch);
                 if (y0 >= y1) continue;
-                for (int s = s0; s < s1; s++) out.push_back(WorkItem{i, s * tile_out(cols, npl), y0, y1});
+                for (int s = s0; s < s1; s++) out.push_back(WorkItem{i, s * tile_out(cols, npl, storage), y0, y1});
             }
         }
     }
@@ -422,19 +423,20 @@ std::vector<WorkItem> build_items(const std::vector<lbm_domain_desc> &d, int chu
 // (15 or 44 of 630 x 60) ran 15-23 % faster in 16-row chunks than in 8-row ones, whose halo
 // rows double the work, while a single 2000 x 100 channel (266 items at 16 rows) ran fastest
 // in 8-row chunks, where more items outweigh the halo.
-int auto_chunk(const std::vector<lbm_domain_desc> &d, int cols, int npl) {
+int auto_chunk(const std::vector<lbm_domain_desc> &d, int cols, int npl, int storage) {
     for (int ch : {64, 48, 32, 24})
-        if (build_items(d, ch, cols, npl).size() >= 4096) return ch;
+        if (build_items(d, ch, cols, npl, storage).size() >= 4096) return ch;
     for (int ch : {16, 12})
-        if (build_items(d, ch, cols, npl).size() >= 512) return ch;
+        if (build_items(d, ch, cols, npl, storage).size() >= 512) return ch;
     return 8;
 }
 
 // Blocks of 4 tile rows (one wavefront per SIMD) measured at least as fast as blocks of 8 for
 // every storage type.
 int default_waves(int) { return 4; }
-// One-wavefront tiles.  Tiles two wavefronts wide (118 output columns of 128) repeat fewer
-// halo columns but measured 3-5 % slower on the sweep (8-wavefront barriers, 2 blocks per CU).
+// One-wavefront tiles.  Tiles two wavefronts wide (120 output columns of 128; 118 with FP64
+// arithmetic) repeat fewer halo columns but measured 3-5 % slower on the sweep (8-wavefront
+// barriers, 2 blocks per CU).
 int default_cols(int) { return 1; }
 // The pair kernel (two node columns per lane) needs FP32 arithmetic and an even width in every
 // domain.  It is offered to lbm_set_tile and the autotuner but is not the built-in choice: at the
@@ -648,8 +650,8 @@ int lbm_create(const lbm_domain_desc *domains, int n, int storage, void *state_d
     c->waves = default_waves(storage);
     c->npl = default_npl(storage, c->desc);
     c->cols = default_cols(storage);
-    c->chunk_rows = auto_chunk(c->desc, c->cols, c->npl);
-    c->items = build_items(c->desc, c->chunk_rows, c->cols, c->npl);
+    c->chunk_rows = auto_chunk(c->desc, c->cols, c->npl, c->storage);
+    c->items = build_items(c->desc, c->chunk_rows, c->cols, c->npl, c->storage);
     if (hipHostMalloc((void **)&c->mass_host, (2 * (size_t)n + 2) * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void **)&c->flag_host, 64) != hipSuccess) {
         delete c;
@@ -746,7 +748,7 @@ int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
         if (sh[2] == 2 && !pairs) continue;
         std::vector<WorkItem> prev;
         for (int ch : {8, 12, 16, 24, 32, 48, 64}) {
-            std::vector<WorkItem> it = build_items(c->desc, ch, sh[1], sh[2]);
+            std::vector<WorkItem> it = build_items(c->desc, ch, sh[1], sh[2], c->storage);
             // a taller chunk that cuts no domain differently is the same schedule
             if (it.size() == prev.size() &&
                 std::equal(it.begin(), it.end(), prev.begin(), [](const WorkItem &a, const WorkItem &b) {
@@ -769,7 +771,7 @@ int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
         c->waves = t.waves;
         c->cols = t.cols;
         c->npl = t.npl;
-        c->items = build_items(c->desc, t.chunk, t.cols, t.npl);
+        c->items = build_items(c->desc, t.chunk, t.cols, t.npl, c->storage);
         if (upload_items(c)) return hipErrorInvalidValue;
         hipError_t e = step_once(c, c->stream);
         if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
@@ -801,7 +803,7 @@ int lbm_autotune(lbm_ctx *c, int steps, void *save_dev, double *out_host) {
     c->waves = best.waves;
     c->cols = best.cols;
     c->npl = best.npl;
-    c->items = build_items(c->desc, best.chunk, best.cols, best.npl);
+    c->items = build_items(c->desc, best.chunk, best.cols, best.npl, c->storage);
     rc = upload_items(c);
     if (rc) return rc;
     drop_graphs(c);
@@ -890,8 +892,8 @@ int lbm_set_tile(lbm_ctx *c, int chunk_rows, int waves, int cols, int cols_per_l
     c->waves = w;
     c->cols = k;
     c->npl = npl;
-    c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc, c->cols, c->npl);
-    c->items = build_items(c->desc, c->chunk_rows, c->cols, c->npl);
+    c->chunk_rows = chunk_rows ? chunk_rows : auto_chunk(c->desc, c->cols, c->npl, c->storage);
+    c->items = build_items(c->desc, c->chunk_rows, c->cols, c->npl, c->storage);
     return upload_items(c);
 }
 

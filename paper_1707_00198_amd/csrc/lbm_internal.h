@@ -15,13 +15,19 @@ constexpr uint32_t FLUID_BND = 1u << 9;   // fluid node with a solid neighbour
 constexpr uint32_t SOLID_BND = 1u << 10;  // solid node with a fluid neighbour
 
 constexpr int TILE_LANES = 64;     // columns per tile row (one wavefront)
-constexpr int HALO = 5;            // halo columns per side: the step's dependency radius next to
-                                   // walls is 4, plus one column for the colour-state stencil
-constexpr int TILE_OUT = TILE_LANES - 2 * HALO;  // output columns of a one-wavefront-wide tile
-// Output columns of a tile: `cols` wavefronts side by side with one column per lane (halo 5 on
-// each side), or one wavefront with two columns per lane (npl = 2: 128 columns, halo 6).
-inline int tile_out(int cols, int npl = 1) {
-    return npl == 2 ? 2 * TILE_LANES - 12 : TILE_LANES * cols - 2 * HALO;
+constexpr int HALO = 5;            // halo rows per side: the step's dependency radius next to
+                                   // walls is 4, plus one row for the colour-state stencil
+// Halo columns per side of the one-column-per-lane step kernel.  With FP64 arithmetic the
+// colour-state column beyond the radius is a lane of the window (5); with FP32 arithmetic it is
+// loaded into two extra LDS columns instead, so every lane gathers and the halo is the radius
+// (4): 56 output columns per wavefront instead of 54.
+constexpr int HALO_X64 = 5, HALO_X32 = 4;
+inline int halo_x(int storage) { return storage == 0 ? HALO_X64 : HALO_X32; }
+// Output columns of a tile: `cols` wavefronts side by side with one column per lane, or one
+// wavefront with two columns per lane (npl = 2: 128 columns, halo 6).  The FP64 storage uses
+// the one-column kernel only.
+inline int tile_out(int cols, int npl, int storage) {
+    return npl == 2 ? 2 * TILE_LANES - 12 : TILE_LANES * cols - 2 * halo_x(storage);
 }
 
 // Per-domain parameters in one arithmetic type, with the constant factors of the collision

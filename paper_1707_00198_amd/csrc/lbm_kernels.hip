@@ -11,9 +11,10 @@
 //                destination from the source node's (c, v) - an exact rewrite of Eqs. 14-16
 //                that stores 12 values per node instead of 18.
 //
-// The step kernel marches a 64-column window (54 output columns plus a 5-column halo on each
-// side: the dependency radius next to walls is 4, plus one column for the colour-state stencil)
-// up a chunk of rows.  Every iteration advances R rows (4 by default) through five stages kept
+// The step kernel marches a 64-column window up a chunk of rows: 56 output columns and a
+// 4-column halo on each side (the dependency radius next to walls), with the colour state of
+// the column beyond each halo in two extra LDS columns; with FP64 arithmetic, 54 output columns
+// and a 5-column halo whose outermost lanes hold that colour state.  Every iteration advances R rows (4 by default) through five stages kept
 // in LDS ring buffers, each lagging the previous one by a row:
 //   A  pull the 9 populations (bounce-back, inlet and outlet completion), rho_R, rho_B, rho^N
 //   B  virtual rho^N on outermost solid nodes (Eq. 29)
@@ -568,10 +569,16 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     constexpr int Q = 2 * R;
     constexpr int TL = TILE_LANES * C;  // columns of the window: C wavefronts side by side
     constexpr uint32_t SB = sizeof(T), CB = sizeof(AT);
+    // Column halo: with FP32 arithmetic every lane gathers, and the colour state of the two
+    // columns just outside the window sits in two extra LDS columns (GO = 1), loaded by lanes 0
+    // and 1; with FP64 arithmetic the outermost lanes hold it (their extra registers would cost
+    // the FP64 kernel an occupancy step).
+    constexpr int HX = sizeof(AT) == 8 ? HALO_X64 : HALO_X32;
+    constexpr int GO = HX == HALO_X32 ? 1 : 0;
     __shared__ AT s_rn[Q][TL];
     __shared__ AT s_nx[Q][TL], s_ny[Q][TL];
     __shared__ AT s_gx[Q][TL], s_gy[Q][TL];
-    __shared__ AT s_c[Q][TL], s_vx[Q][TL], s_vy[Q][TL];
+    __shared__ AT s_c[Q][TL + 2 * GO], s_vx[Q][TL + 2 * GO], s_vy[Q][TL + 2 * GO];
     __shared__ AT s_wx[Q][TL], s_wy[Q][TL];
     __shared__ uint16_t s_m[Q][TL];
     // per row slot and wavefront column: the row has an outermost solid node in that column
@@ -587,7 +594,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     // row slots then live in scalar registers
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / TL);
     const int lane = threadIdx.x % TL;
-    const int base = x0 - HALO;
+    const int base = x0 - HX;
     const int X = base + lane;
     // Node column of the lane: periodic in x, or clamped to the edge columns of an open x axis.
     // The x-1 / x+1 stencil neighbours are always the adjacent lanes.  At an open axis the
@@ -598,8 +605,11 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     const bool edge_item = D.open_x && (base < 0 || base + TL > D.nx);
     const int edge_lane = xe != X && D.open_x ? xe - base : -1;
     const int lanes_of[3] = {lane - 1, lane, lane + 1};
-    const bool out_lane = lane >= HALO && lane < TL - HALO && X < D.nx;
-    const bool gather_lane = lane >= 1 && lane < TL - 1;
+    const bool out_lane = lane >= HX && lane < TL - HX && X < D.nx;
+    const bool gather_lane = GO || (lane >= 1 && lane < TL - 1);
+    // node column of the ghost colour-state column a lane loads (lane 0: left, lane 1: right)
+    const int xg = lane == 0 ? base - 1 : base + TL;
+    const int xge = D.open_x ? min(max(xg, 0), D.nx - 1) : wrap(xg, D.nx);
     ParC<AT> &P = par(D, AT());
     const AT eps = P.eps;
     const bool rec_cl = A.diag && A.cl_count != nullptr && dom == A.cl_dom;
@@ -647,13 +657,23 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     uint32_t qm = 0;
     struct Colour {
         AT c, vx, vy;
+        AT gc, gvx, gvy;  // ghost column (GO only)
     };
-    Colour cset[2] = {{AT(0), AT(0), AT(0)}, {AT(0), AT(0), AT(0)}};
+    Colour cset[2] = {{AT(0), AT(0), AT(0), AT(0), AT(0), AT(0)}, {AT(0), AT(0), AT(0), AT(0), AT(0), AT(0)}};
     auto load_colour = [&](int yc, Colour &cs) {
-        const uint32_t vo = row_ok_c(yc) ? node_of(yc) * CB : NOWHERE;
+        const bool ok = row_ok_c(yc);
+        const uint32_t vo = ok ? node_of(yc) * CB : NOWHERE;
         cs.c = Buf<AT>::load(c_in, vo, 0);
         cs.vx = Buf<AT>::load(c_in, vo, CP);
         cs.vy = Buf<AT>::load(c_in, vo, 2 * CP);
+        if constexpr (GO) {
+            const uint32_t vg = ok && lane < 2
+                                    ? ((uint32_t)D.off + (uint32_t)wrap(yc, D.ny) * (uint32_t)D.nx + (uint32_t)xge) * CB
+                                    : NOWHERE;
+            cs.gc = Buf<AT>::load(c_in, vg, 0);
+            cs.gvx = Buf<AT>::load(c_in, vg, CP);
+            cs.gvy = Buf<AT>::load(c_in, vg, 2 * CP);
+        }
     };
     auto load_mask = [&](int y) {
         qm = Buf<uint16_t>::load(r_mask, row_ok_a(y) ? node_of(y) * 2u : NOWHERE, 0);
@@ -722,9 +742,17 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
     // colour row yc into the LDS ring
     auto put_colour = [&](int yc, const Colour &cs) {
         const int sl = yc & (Q - 1);
-        s_c[sl][lane] = cs.c;
-        s_vx[sl][lane] = cs.vx;
-        s_vy[sl][lane] = cs.vy;
+        s_c[sl][lane + GO] = cs.c;
+        s_vx[sl][lane + GO] = cs.vx;
+        s_vy[sl][lane + GO] = cs.vy;
+        if constexpr (GO) {
+            if (lane < 2) {
+                const int gl = lane == 0 ? 0 : TL + 1;
+                s_c[sl][gl] = cs.gc;
+                s_vx[sl][gl] = cs.gvx;
+                s_vy[sl][gl] = cs.gvy;
+            }
+        }
     };
     // one row of outputs: populations, then the colour state (c, vx, vy)
     auto store_row = [&](uint32_t vf, uint32_t vc, const AT (&o)[9], AT c, AT bx, AT by) {
@@ -766,7 +794,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
             finish_gather<true>(A, D, xe, yw, m, nb, !A.diag, dn, rRn, rBn,
                                 [&](int a, AT &c, AT &vx, AT &vy) {
                                     const int s2 = (ya - EY[a]) & (Q - 1);
-                                    const int l2 = lanes_of[1 - EX[a]];
+                                    const int l2 = lanes_of[1 - EX[a]] + GO;
                                     c = s_c[s2][l2];
                                     vx = s_vx[s2][l2];
                                     vy = s_vy[s2][l2];
@@ -827,7 +855,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
             {
                 const int yb = r + R - 1 + w;
                 const int sl = yb & (Q - 1);
-                if (lane >= 2 && lane < TL - 2 && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
+                if (lane >= HX - 3 && lane < TL - (HX - 3) && yb >= y0 - HALO + 2 && yb < y1 + HALO - 2) {
                     const uint32_t m = s_m[sl][lane];
                     if ((m & SOLID_BND) && surface_energy) {
                         s_rn[sl][lane] = P.cos_t;  // surface-energy rule
@@ -851,7 +879,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
         {
             const int yc = r + R - 2 + w;
             const int sl = yc & (Q - 1);
-            if (lane >= 3 && lane < TL - 3 && yc >= y0 - HALO + 3 && yc < y1 + HALO - 3) {
+            if (lane >= HX - 2 && lane < TL - (HX - 2) && yc >= y0 - HALO + 3 && yc < y1 + HALO - 3) {
                 const uint32_t m = s_m[sl][lane];
                 AT gx = AT(0), gy = AT(0), nx = AT(0), ny = AT(0);
                 if (!(m & SELF_SOLID)) {
@@ -891,7 +919,7 @@ __global__ __launch_bounds__(TILE_LANES *R *C, sizeof(typename Codec<T>::AT) == 
             {
                 const int yd = r + R - 3 + w;
                 const int sl = yd & (Q - 1);
-                if (lane >= 4 && lane < TL - 4 && yd >= y0 - 1 && yd < y1 + 1) {
+                if (lane >= HX - 1 && lane < TL - (HX - 1) && yd >= y0 - 1 && yd < y1 + 1) {
                     const uint32_t m = s_m[sl][lane];
                     if (m & SOLID_BND) {
                         AT numx = AT(0), numy = AT(0), den = AT(0);

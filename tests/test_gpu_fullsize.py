@@ -73,8 +73,8 @@ def test_fullsize_sweep_sampled_channels(storage, rel):
     from paper_1707_00198_amd.lbm import Lattice
     setups = W.cfg_sweep()
     lat = Lattice(setups, storage=storage)
-    # the built-in launch configuration: 64-row chunks of 54-column strips, 4 wavefronts
-    assert lat.tile == dict(chunk_rows=64, waves=4, cols=1, items=31744, cols_per_lane=1)
+    # the built-in launch configuration: 64-row chunks of 56-column strips, 4 wavefronts
+    assert lat.tile == dict(chunk_rows=64, waves=4, cols=1, items=30592, cols_per_lane=1)
     lat.set_graph(10)
     lat.step(30)
     lat.set_graph(0)
