@@ -14,9 +14,8 @@
 // The step kernel marches a 64-column window up a chunk of rows: 56 output columns and a
 // 4-column halo on each side (the dependency radius next to walls), with the colour state of
 // the column beyond each halo in two extra LDS columns; with FP64 arithmetic, 54 output columns
-// and a 5-column halo whose outermost lanes hold that colour state.  Every iteration advances
-// R rows (4 by default) through five stages kept in LDS ring buffers, each lagging the previous
-// one by a row:
+// and a 5-column halo whose outermost lanes hold that colour state.  Every iteration advances R rows (4 by default) through five stages kept
+// in LDS ring buffers, each lagging the previous one by a row:
 //   A  pull the 9 populations (bounce-back, inlet and outlet completion), rho_R, rho_B, rho^N
 //   B  virtual rho^N on outermost solid nodes (Eq. 29)
 //   C  colour gradient (Eq. 28), wetting correction on outermost fluid nodes (Eqs. 30-36),
