@@ -99,6 +99,31 @@ def test_parity_ragged_and_tiny_domains_batched():
         assert_parity(lat.pops(d), oracle_for(s).step(60).pops(), what=s.name)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "c16"])
+def test_reduced_storage_ragged_and_tiny_domains(storage):
+    """The ragged and tiny domains above in the FP32-arithmetic builds, whose tiles take the
+    colour state beyond the window from two extra LDS columns (56 output columns of 64): domains
+    one column wide, narrower than a tile, exactly one tile (56) and one column past it (57, 113),
+    open x with nx = 2 and 61.  After 20 steps the oracle advances the GPU state by one step and
+    the GPU's next step must agree within the storage's rounding of each population's deviation
+    from w rho0 (2^-22 FP32, 2^-10 binary16, 2^-11 the 11-bit-fraction format) plus 2e-6."""
+    weights = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    rel = {"f32": 2.0 ** -22, "f16": 2.0 ** -10, "c16": 2.0 ** -11}[storage]
+    cases = ragged_cases()
+    lat = lattice(cases, storage).step(20)
+    before = [lat.pops(d) for d in range(len(cases))]
+    lat.step(1)
+    for d, s in enumerate(cases):
+        o = oracle_for(s)
+        o.set_pops(before[d])
+        ref = o.step(1).pops()
+        got = lat.pops(d)
+        dev = np.abs(ref.sum(axis=0) - weights[:, None, None] * s.params["rho0"] * (s.solid == 0))
+        worst = (np.abs(got - ref) / (dev * rel + 2e-6)[None]).max()
+        print(f"{storage} {s.name}: max error / tolerance = {worst:.3f}", flush=True)
+        assert np.isfinite(got).all() and worst <= 1.0
+
+
 def test_parity_batched_uneven_channels():
     cases = [W.fingering_channel(nx=16 * h, h=h, x_interface=2.0 * h + j, M=m, theta_deg=t,
                                  ca=0.1, nu_r=0.5, sigma=0.05, name=f"ch{h}")
