@@ -441,7 +441,7 @@ int default_cols(int) { return 1; }
 // The pair kernel (two node columns per lane) needs FP32 arithmetic and an even width in every
 // domain.  It is offered to lbm_set_tile and the autotuner but is not the built-in choice: at the
 // two wavefronts per SIMD its register use allows, it measured slower than the one-column kernel
-// at four (sweep 33.4 against 47.8 GLUPS).
+// at four (binary16 sweep 33.9 against 50.7 GLUPS).
 bool pair_allowed(int storage, const std::vector<lbm_domain_desc> &d) {
     if (storage == 0) return false;
     for (const auto &q : d)
